@@ -1,0 +1,187 @@
+"""FP64 CPU oracle for the local phases of the pencil 3-D FFT (AccFFT, Sec. 2).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product path (the
+HIP library and its Python binding) never imports, loads or calls it, and it
+shares no code with that path.
+
+Contents
+  * ``fft3d_c2c / fft3d_r2c / fft3d_c2r / fft_axis`` -- ctypes wrappers around
+    ``oracle_fft.c`` (row-column mixed-radix Cooley-Tukey, Algorithm 1 order).
+  * ``poisson_half / poisson_solve`` -- the spectral Poisson operator
+    (Sec. 1 lists "fast spectral operators"; the operator is the textbook
+    periodic solve -1/|k|^2 with the k = 0 mode zeroed).
+  * ``pencil_pack / pencil_unpack / pencil_share_forward`` -- the pack, loopback
+    exchange and unpack maps of the row all-to-all (Sec. 2, pencil paragraph,
+    and Algorithm 1, steps 1-3), written as numpy permutations.
+  * ``brute`` submodule -- the direct O(N^2) DFT used to pin the FFT.
+
+Conventions (readings of the paper, listed in the design notes): forward uses
+exp(-2 pi i ...), inverse exp(+2 pi i ...), neither is scaled; arrays are
+C-order [x][y][z] in both domains; R2C keeps k2 = 0 .. n2 // 2.
+
+Parity status: every function here is pinned by the CPU tests; none is
+parity unpinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle_fft.c")
+_LIB = os.path.join(_HERE, "liboracle_fft.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle_fft.c`` into ``liboracle_fft.so`` with gcc + OpenMP."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB)
+            dp = ctypes.POINTER(ctypes.c_double)
+            i64 = ctypes.c_int64
+            ci = ctypes.c_int
+            lib.oracle_fft1d.argtypes = [dp, i64, ci, ci]
+            lib.oracle_fft3d_c2c.argtypes = [dp, ci, ci, ci, ci]
+            lib.oracle_fft_axis.argtypes = [dp, i64, ci, i64, ci]
+            lib.oracle_fft3d_r2c.argtypes = [dp, dp, ci, ci, ci]
+            lib.oracle_fft3d_c2r.argtypes = [dp, dp, ci, ci, ci]
+            lib.oracle_poisson_half.argtypes = [dp, ci, ci, ci, ctypes.c_double]
+            for f in (lib.oracle_fft1d, lib.oracle_fft3d_c2c, lib.oracle_fft_axis,
+                      lib.oracle_fft3d_r2c, lib.oracle_fft3d_c2r, lib.oracle_poisson_half):
+                f.restype = None
+            _lib = lib
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _as_c128(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x), dtype=np.complex128).copy()
+
+
+def fft1d(x, sign: int = -1) -> np.ndarray:
+    """Unscaled 1-D DFT of every row of a 2-D (batch, n) array."""
+    a = _as_c128(x)
+    if a.ndim == 1:
+        a = a[None, :]
+    _load().oracle_fft1d(_dptr(a), a.shape[0], a.shape[1], int(sign))
+    return a
+
+
+def fft3d_c2c(x, sign: int = -1) -> np.ndarray:
+    """Unscaled 3-D DFT, z then y then x (Algorithm 1, left column)."""
+    a = _as_c128(x)
+    n0, n1, n2 = a.shape
+    _load().oracle_fft3d_c2c(_dptr(a), n0, n1, n2, int(sign))
+    return a
+
+
+def fft_axis(x, axis: int, sign: int = -1) -> np.ndarray:
+    """Unscaled 1-D DFT along one axis of an N-D complex array."""
+    a = _as_c128(x)
+    shape = a.shape
+    outer = int(np.prod(shape[:axis], dtype=np.int64))
+    inner = int(np.prod(shape[axis + 1:], dtype=np.int64))
+    _load().oracle_fft_axis(_dptr(a), outer, shape[axis], inner, int(sign))
+    return a
+
+
+def fft3d_r2c(x) -> np.ndarray:
+    """Real [n0][n1][n2] -> half spectrum [n0][n1][n2//2+1], unscaled."""
+    a = np.ascontiguousarray(np.asarray(x), dtype=np.float64)
+    n0, n1, n2 = a.shape
+    out = np.empty((n0, n1, n2 // 2 + 1), dtype=np.complex128)
+    _load().oracle_fft3d_r2c(_dptr(a), _dptr(out), n0, n1, n2)
+    return out
+
+
+def fft3d_c2r(y, n2: int) -> np.ndarray:
+    """Half spectrum [n0][n1][n2//2+1] -> real [n0][n1][n2], unscaled; the
+    imaginary parts at k2 = 0 and (even n2) k2 = n2/2 are discarded."""
+    a = _as_c128(y)
+    n0, n1, n2c = a.shape
+    if n2c != n2 // 2 + 1:
+        raise ValueError("half spectrum has %d entries along z, n2=%d needs %d"
+                         % (n2c, n2, n2 // 2 + 1))
+    out = np.empty((n0, n1, n2), dtype=np.float64)
+    _load().oracle_fft3d_c2r(_dptr(a), _dptr(out), n0, n1, n2)
+    return out
+
+
+def poisson_half(yhat, n2: int, scale: float = 1.0) -> np.ndarray:
+    """U = -scale * F / |k|^2 on the half spectrum, U[0,0,0] = 0."""
+    a = _as_c128(yhat)
+    n0, n1, n2c = a.shape
+    if n2c != n2 // 2 + 1:
+        raise ValueError("bad half-spectrum shape")
+    _load().oracle_poisson_half(_dptr(a), n0, n1, n2, float(scale))
+    return a
+
+
+def poisson_solve(f) -> np.ndarray:
+    """Periodic Poisson solve lap(u) = f on [0, 2 pi)^3: R2C, multiply by
+    -1/|k|^2 (k = 0 zeroed), C2R, divide by N."""
+    f = np.asarray(f, dtype=np.float64)
+    n0, n1, n2 = f.shape
+    n = n0 * n1 * n2
+    fh = fft3d_r2c(f)
+    uh = poisson_half(fh, n2, 1.0)
+    return fft3d_c2r(uh, n2) / n
+
+
+# ---- pencil share: pack, loopback exchange, unpack (Algorithm 1, steps 1-3) ----
+
+def pencil_pack(ahat, p1: int) -> np.ndarray:
+    """Row all-to-all send layout S[j][i0][i1][m] = Ahat[i0][i1][j*M + m] with
+    M = n2 / p1: block j holds the k2 range destined for row peer j."""
+    a = np.asarray(ahat)
+    n0l, n1l, n2 = a.shape
+    if n2 % p1:
+        raise ValueError("p1 must divide n2")
+    m = n2 // p1
+    return np.ascontiguousarray(a.reshape(n0l, n1l, p1, m).transpose(2, 0, 1, 3))
+
+
+def pencil_unpack(r, n1l: int) -> np.ndarray:
+    """Receive layout R[j][i0][i1][m] -> B[i0][j*n1l + i1][m]: the block from
+    row peer j supplies the y range j*n1l .. (j+1)*n1l."""
+    r = np.asarray(r)
+    p1, n0l, n1l_, m = r.shape
+    if n1l_ != n1l:
+        raise ValueError("receive block has the wrong y extent")
+    return np.ascontiguousarray(r.transpose(1, 0, 2, 3).reshape(n0l, p1 * n1l, m))
+
+
+def pencil_share_forward(a, p1: int) -> np.ndarray:
+    """One rank's local phases with a loopback exchange: z-DFT of the
+    n0l x n1l x n2 share, pack, receive buffer = send buffer, unpack, then the
+    y-DFT of length p1 * n1l along axis 1."""
+    a = np.asarray(a)
+    n0l, n1l, n2 = a.shape
+    ahat = fft_axis(a, 2, -1)
+    s = pencil_pack(ahat, p1)
+    b = pencil_unpack(s, n1l)
+    return fft_axis(b, 1, -1)
