@@ -1,0 +1,220 @@
+/*
+ * mifft.h -- C ABI of the MI355X-native local phases of the pencil 3-D FFT.
+ *
+ * The library computes, on one gfx950 GPU, the data-parallel local phases of
+ * the distributed 3-D FFT of AccFFT (Gholami, Hill, Malhotra, Biros, Sec. 2,
+ * Algorithm 1): batched 1-D FFTs along z, then y, then x, joined by the pack /
+ * unpack steps that reshape a pencil for the row all-to-all, with R2C / C2R
+ * pre- and post-processing, in single and double precision.
+ *
+ * Conventions (the paper leaves them open; these are the readings taken):
+ *   - forward uses exp(-2 pi i jk/n), inverse exp(+2 pi i jk/n), and neither
+ *     is scaled, so inverse(forward(x)) = n0*n1*n2 * x;
+ *   - arrays are dense C-order [n0][n1][n2] (x slowest, z fastest) in both
+ *     domains: the frequency layout equals the spatial one (Sec. 2, slab
+ *     paragraph; at P0 = P1 = 1 the x-pencil and z-pencil layouts of
+ *     Algorithm 1 are the same array);
+ *   - complex values are interleaved (re, im): float2 / double2;
+ *   - an R2C spectrum is [n0][n1][n2/2 + 1]; C2R discards the imaginary parts
+ *     of its k2 = 0 and k2 = n2/2 entries (after the x and y inverses), which
+ *     defines the result for input that is not Hermitian.
+ *
+ * Ownership: the caller owns every data, workspace and buffer pointer; a plan
+ * owns its twiddle tables and its default workspace.  Every pointer passed to
+ * an execute call is a device pointer on the plan's device.  Execute calls
+ * only enqueue kernels on `stream` (a hipStream_t; NULL means the default
+ * stream): they never allocate, synchronise or block, so they may be captured
+ * into a HIP graph.  The caller must make sure no work on a plan is in flight
+ * before destroying it.
+ *
+ * Errors: no exception crosses the ABI; every call returns an mifft_status.
+ * Arguments are checked on the host before any HIP call, so argument errors
+ * are reported identically with or without a GPU.  Kernel faults surface at
+ * the caller's next synchronisation, as with any stream API.  The message of
+ * the last failing call on the calling thread is returned by
+ * mifft_last_error().
+ */
+#ifndef MIFFT_H
+#define MIFFT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mifft_plan_s* mifft_plan;   /* opaque, owned by the library */
+typedef struct mifft_batch_s* mifft_batch; /* opaque, owned by the library */
+
+typedef enum { MIFFT_C2C = 0, MIFFT_R2C = 1 } mifft_kind; /* an R2C plan also runs C2R */
+typedef enum { MIFFT_FP32 = 0, MIFFT_FP64 = 1 } mifft_prec;
+
+typedef enum {
+    MIFFT_OK = 0,
+    MIFFT_ERR_INVALID = 1,     /* null pointer, size < 1, bad enum, misaligned pointer */
+    MIFFT_ERR_UNSUPPORTED = 2, /* prime factor > 5, odd n2 for R2C, axis too long,
+                                  process grid that does not divide the grid */
+    MIFFT_ERR_NOMEM = 3,       /* device allocation failed */
+    MIFFT_ERR_DEVICE = 4,      /* any HIP runtime error, including "no device" */
+    MIFFT_ERR_BADPLAN = 5      /* destroyed / foreign handle, or wrong plan kind */
+} mifft_status;
+
+/* Plan flags. */
+#define MIFFT_HEURISTIC 0u /* kernel variants from the built-in heuristic */
+#define MIFFT_TUNE 1u      /* time the candidate variants on the device and keep the
+                              fastest (in the spirit of the MEASURE planning the paper
+                              uses, Sec. 3, Implementation Details); consults and
+                              updates the wisdom file named by MIFFT_WISDOM */
+
+/* Longest axis a single-pass kernel handles. */
+#define MIFFT_MAX_AXIS 1024
+
+/* Pencil stage bits for mifft_execute_pencil_stages. */
+#define MIFFT_STAGE_Z 1u      /* batched z-FFT of the local share (Algorithm 1, step 1) */
+#define MIFFT_STAGE_PACK 2u   /* pack into the row all-to-all send layout (Sec. 2) */
+#define MIFFT_STAGE_UNPACK 4u /* unpack the receive layout (Sec. 2) */
+#define MIFFT_STAGE_Y 8u      /* batched y-FFT (Algorithm 1, step 3) */
+
+/*
+ * mifft_plan_create -- plan a 3-D transform of an n0 x n1 x n2 grid.
+ * Defines: the problem statement of Sec. 1 (Contributions: an N0 x N1 x N2
+ * array, R2C / C2C / C2R, single and double precision).
+ *   out    receives the handle (unchanged on error)
+ *   n0..2  grid extents, each 1 .. MIFFT_MAX_AXIS with no prime factor above 5;
+ *          R2C needs an even n2
+ *   kind   MIFFT_C2C or MIFFT_R2C (the R2C plan runs C2R as its inverse)
+ *   prec   MIFFT_FP32 (complex64 / float32) or MIFFT_FP64
+ *   flags  MIFFT_HEURISTIC or MIFFT_TUNE
+ * Allocates device twiddle tables (generated in FP64 on the GPU, rounded to
+ * nearest for FP32 plans) and the default workspace on the current device.
+ */
+int mifft_plan_create(mifft_plan* out, int n0, int n1, int n2, int kind, int prec,
+                      unsigned flags);
+
+/*
+ * mifft_execute_forward -- forward transform (Algorithm 1, left column:
+ * z-FFT, y-FFT, x-FFT; at P0 = P1 = 1 both exchanges are identities).
+ *   C2C: in, out complex [n0][n1][n2]; in == out is allowed.
+ *   R2C: in real [n0][n1][n2], out complex [n0][n1][n2/2+1]; must not overlap.
+ * `in` is not modified unless in == out.  Uses the plan's default workspace.
+ */
+int mifft_execute_forward(mifft_plan plan, const void* in, void* out, void* stream);
+
+/*
+ * mifft_execute_inverse -- unscaled inverse transform (Algorithm 1, right
+ * column: x-IFFT, y-IFFT, z-IFFT).
+ *   C2C: in, out complex [n0][n1][n2]; in == out is allowed.
+ *   C2R: in complex [n0][n1][n2/2+1], out real [n0][n1][n2]; must not overlap;
+ *        `in` is preserved (the intermediate lives in the workspace).
+ */
+int mifft_execute_inverse(mifft_plan plan, const void* in, void* out, void* stream);
+
+/* Bytes of workspace an execute call of this plan needs (0 if none). */
+size_t mifft_workspace_bytes(mifft_plan plan);
+
+/* As above with a caller-owned workspace of at least mifft_workspace_bytes
+ * bytes (NULL when that is 0).  Two execute calls of one plan may run
+ * concurrently on different streams only through these variants, each with
+ * its own workspace; the plain variants share the plan's default one. */
+int mifft_execute_forward_ws(mifft_plan plan, const void* in, void* out, void* ws,
+                             void* stream);
+int mifft_execute_inverse_ws(mifft_plan plan, const void* in, void* out, void* ws,
+                             void* stream);
+
+/*
+ * mifft_plan_destroy -- free the plan's device memory.  NULL is a no-op that
+ * returns MIFFT_OK; a handle that is not live returns MIFFT_ERR_BADPLAN.
+ */
+int mifft_plan_destroy(mifft_plan plan);
+
+/* Message of the last failing call on this thread ("" if none).  The pointer
+ * stays valid until the next mifft call on the same thread. */
+const char* mifft_last_error(void);
+
+/*
+ * mifft_plan_create_pencil -- plan one rank's share of the pencil-decomposed
+ * forward transform of an N0 x N1 x N2 C2C grid on a p0 x p1 process grid
+ * (Sec. 2, pencil paragraph; Algorithm 1, steps 1-3).  The share is the
+ * local array A[N0/p0][N1/p1][N2]; with M = N2/p1 the stages compute
+ *   Z:      Ahat = z-FFT of A along its last axis (length N2)
+ *   PACK:   S[j][i0][i1][m] = Ahat[i0][i1][j*M + m]   (send block j -> row peer j)
+ *   UNPACK: B[i0][j*(N1/p1) + i1][m] = R[j][i0][i1][m] (R = receive buffer)
+ *   Y:      y-FFT of B along its middle axis (length N1)
+ * The row all-to-all between PACK and UNPACK is not performed here: on one
+ * GPU the caller passes recvbuf == sendbuf (loopback) or moves the blocks
+ * itself.  Needs kind = MIFFT_C2C and N0 % p0 == N1 % p1 == N2 % p1 == 0.
+ */
+int mifft_plan_create_pencil(mifft_plan* out, int n0, int n1, int n2, int p0, int p1,
+                             int kind, int prec, unsigned flags);
+
+/*
+ * mifft_execute_pencil_stages -- run the stages named in stage_mask, in the
+ * order Z, PACK, UNPACK, Y.  Buffers (all complex, dense):
+ *   in       A, (N0/p0) x (N1/p1) x N2           read by Z (or by PACK without Z);
+ *                                                Z without PACK overwrites it
+ *   sendbuf  S, p1 x (N0/p0) x (N1/p1) x M       written by PACK
+ *   recvbuf  R, same shape as S                  read by UNPACK
+ *   out      B, (N0/p0) x N1 x M                 written by UNPACK, transformed by Y
+ * Z without PACK writes Ahat to `in` in place; Z with PACK writes S directly
+ * (pack fused into the z-FFT's stores).  UNPACK with Y reads R directly
+ * (unpack fused into the y-FFT's loads).  Y without UNPACK transforms `out`
+ * in place.  Buffers a selected stage does not touch may be NULL.
+ */
+int mifft_execute_pencil_stages(mifft_plan plan, unsigned stage_mask, void* in,
+                                void* sendbuf, void* recvbuf, void* out, void* stream);
+
+/*
+ * mifft_poisson_solve -- periodic Poisson solve lap(u) = f on [0, 2 pi)^3
+ * with an R2C plan: R2C forward, multiply the half spectrum by
+ * -1 / (|k|^2 n0 n1 n2) with the k = 0 mode set to zero (signed wavenumbers
+ * k' = k for k < n/2, else k - n, along x and y), C2R inverse.  One of the
+ * "fast spectral operators" listed in Sec. 1.  f and u are real
+ * [n0][n1][n2]; ws is a caller-owned workspace of mifft_poisson_ws_bytes
+ * bytes, or NULL to use the plan's default one (then calls on one plan must
+ * not overlap).  f is preserved; f and u must not overlap.
+ */
+size_t mifft_poisson_ws_bytes(mifft_plan plan);
+int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void* stream);
+
+/*
+ * mifft_batch_create -- plan `count` independent 3-D C2C transforms of
+ * uneven sizes (dims holds n0, n1, n2 per transform) that run as ONE
+ * launch of a persistent kernel: workgroups pull (transform, pass, tile)
+ * work items from a device queue in dependency order.  Per-length kernel
+ * variants come from the same planner as single plans (MIFFT_TUNE times
+ * them).  The execute call is graph-capturable; see mifft_batch_graph_launch.
+ * Planning in the spirit of the FFTW / SPIRAL search the paper cites (Sec. 1).
+ */
+int mifft_batch_create(mifft_batch* out, int count, const int* dims, int kind, int prec,
+                       unsigned flags);
+
+/* Forward transforms of the whole batch: in[t], out[t] are device pointers
+ * to complex [n0][n1][n2] arrays; in[t] == out[t] is allowed.  The pointer
+ * arrays are host arrays read during the call. */
+int mifft_batch_execute_forward(mifft_batch batch, void* const* in, void* const* out,
+                                void* stream);
+
+/* Capture one mifft_batch_execute_forward with these buffers into a HIP
+ * graph owned by the batch, then launch the instantiated graph on `stream`.
+ * Later calls with the same pointer arrays replay the graph. */
+int mifft_batch_graph_launch(mifft_batch batch, void* const* in, void* const* out,
+                             void* stream);
+
+int mifft_batch_destroy(mifft_batch batch);
+
+/*
+ * Introspection for tests, benchmarks and the autotuner.
+ * mifft_plan_describe writes a NUL-terminated description of the passes of
+ * the plan (kernel variant, length, stride, batch, launch shape), one line
+ * per pass, into buf (at most len bytes) and returns MIFFT_OK.
+ */
+int mifft_plan_describe(mifft_plan plan, char* buf, size_t len);
+
+/* Version string of the library build. */
+const char* mifft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIFFT_H */

@@ -1,0 +1,72 @@
+"""ctypes loader for libmifft.so (the C ABI of include/mifft.h).
+
+The binding only marshals arguments: every step of a transform runs in the
+library's HIP kernels.  There is no fallback: if the library is missing or
+does not load, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmifft.so")
+
+MIFFT_C2C, MIFFT_R2C = 0, 1
+MIFFT_FP32, MIFFT_FP64 = 0, 1
+MIFFT_HEURISTIC, MIFFT_TUNE = 0, 1
+MIFFT_STAGE_Z, MIFFT_STAGE_PACK, MIFFT_STAGE_UNPACK, MIFFT_STAGE_Y = 1, 2, 4, 8
+STATUS = {0: "MIFFT_OK", 1: "MIFFT_ERR_INVALID", 2: "MIFFT_ERR_UNSUPPORTED",
+          3: "MIFFT_ERR_NOMEM", 4: "MIFFT_ERR_DEVICE", 5: "MIFFT_ERR_BADPLAN"}
+
+# name -> (restype, argtypes); mirrors include/mifft.h
+_vp, _cvp, _i, _u, _sz = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_size_t
+_vpp = ctypes.POINTER(ctypes.c_void_p)
+SIGNATURES = {
+    "mifft_plan_create": (_i, [_vpp, _i, _i, _i, _i, _i, _u]),
+    "mifft_execute_forward": (_i, [_vp, _cvp, _vp, _vp]),
+    "mifft_execute_inverse": (_i, [_vp, _cvp, _vp, _vp]),
+    "mifft_workspace_bytes": (_sz, [_vp]),
+    "mifft_execute_forward_ws": (_i, [_vp, _cvp, _vp, _vp, _vp]),
+    "mifft_execute_inverse_ws": (_i, [_vp, _cvp, _vp, _vp, _vp]),
+    "mifft_plan_destroy": (_i, [_vp]),
+    "mifft_last_error": (ctypes.c_char_p, []),
+    "mifft_plan_create_pencil": (_i, [_vpp, _i, _i, _i, _i, _i, _i, _i, _u]),
+    "mifft_execute_pencil_stages": (_i, [_vp, _u, _vp, _vp, _vp, _vp, _vp]),
+    "mifft_poisson_ws_bytes": (_sz, [_vp]),
+    "mifft_poisson_solve": (_i, [_vp, _cvp, _vp, _vp, _vp]),
+    "mifft_batch_create": (_i, [_vpp, _i, ctypes.POINTER(ctypes.c_int), _i, _i, _u]),
+    "mifft_batch_execute_forward": (_i, [_vp, _vpp, _vpp, _vp]),
+    "mifft_batch_graph_launch": (_i, [_vp, _vpp, _vpp, _vp]),
+    "mifft_batch_destroy": (_i, [_vp]),
+    "mifft_plan_describe": (_i, [_vp, ctypes.c_char_p, _sz]),
+    "mifft_version": (ctypes.c_char_p, []),
+}
+
+
+class MifftError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        self.status_name = STATUS.get(status, str(status))
+        super().__init__("%s: %s (%s)" % (where, message, self.status_name))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmifft.so is not built: run `python -m paper_1506_07933_amd.build` "
+                          "(expected at %s)" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def check(status: int, where: str) -> None:
+    if status != 0:
+        msg = lib.mifft_last_error()
+        raise MifftError(status, where, msg.decode() if msg else "")

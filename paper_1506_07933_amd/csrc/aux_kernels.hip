@@ -1,0 +1,171 @@
+// aux_kernels.hip -- twiddle generation, spectral Poisson multiply, standalone
+// pack / unpack of the row all-to-all, and a plain copy.
+#include "aux_kernels.hpp"
+
+namespace mifft {
+
+// w[m] = exp(-2 pi i m / n), m = 0 .. n-1, evaluated in FP64 and rounded to
+// nearest in T.  The angle is split exactly in integers into whole quarter
+// turns q and a remainder; the remainder angle is folded into [0, pi/4] so
+// sincospi only sees a small argument, and multiples of a quarter turn give
+// exact 0 and +-1.
+template <typename T> __global__ void k_twiddles(cx<T>* w, int n)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const long long q = (4LL * m) / n;
+    const long long r = 4LL * m - q * n;
+    double s, c;
+    if (2 * r <= n) {
+        sincospi((double)r / (2.0 * (double)n), &s, &c);
+    } else {
+        double s2, c2;
+        sincospi((double)(n - r) / (2.0 * (double)n), &s2, &c2);
+        s = c2;
+        c = s2;
+    }
+    double cr, sr; // cos, sin of the full angle 2 pi m / n
+    switch ((int)q) {
+    case 0: cr = c; sr = s; break;
+    case 1: cr = -s; sr = c; break;
+    case 2: cr = -c; sr = -s; break;
+    default: cr = s; sr = -c; break;
+    }
+    w[m] = cx<T>{(T)cr, (T)(-sr)};
+}
+
+template <typename T>
+hipError_t launch_twiddles(cx<T>* w, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_twiddles<T>, dim3((n + 255) / 256), dim3(256), 0, s, w, n);
+    return hipGetLastError();
+}
+
+// U[i0][i1][k2] *= -scale / |k|^2 on the half spectrum, U[0][0][0] = 0.
+template <typename T>
+__global__ void k_poisson(cx<T>* u, int n0, int n1, int n2c, T scale, long long total)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int k2 = (int)(i % n2c);
+    const long long r = i / n2c;
+    const int i1 = (int)(r % n1);
+    const int i0 = (int)(r / n1);
+    const long long k0 = (2 * i0 < n0) ? i0 : i0 - n0;
+    const long long k1 = (2 * i1 < n1) ? i1 : i1 - n1;
+    const long long kk = k0 * k0 + k1 * k1 + (long long)k2 * k2;
+    cx<T> v = u[i];
+    if (kk == 0) {
+        v = cx<T>{T(0), T(0)};
+    } else {
+        const T f = -scale / (T)kk;
+        v.x *= f;
+        v.y *= f;
+    }
+    u[i] = v;
+}
+
+template <typename T>
+hipError_t launch_poisson(cx<T>* u, int n0, int n1, int n2c, T scale, hipStream_t s)
+{
+    const long long total = (long long)n0 * n1 * n2c;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_poisson<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, u, n0,
+                       n1, n2c, scale, total);
+    return hipGetLastError();
+}
+
+// Pack: S[j][i0][i1][m] = A[i0][i1][j*M + m].  One thread per element of S;
+// a run of M contiguous elements of A becomes a run of M in S.
+template <typename T>
+__global__ void k_pack(const cx<T>* __restrict__ a, cx<T>* __restrict__ s, long long lines, int p1,
+                       int M, long long total)
+{
+    const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= total) return;
+    const int m = (int)(o % M);
+    const long long rest = o / M;
+    const long long line = rest % lines; // i0 * n1l + i1
+    const int j = (int)(rest / lines);
+    s[o] = a[line * ((long long)p1 * M) + (long long)j * M + m];
+}
+
+// Unpack: B[i0][j*n1l + i1][m] = R[j][i0][i1][m].  One thread per element of B.
+template <typename T>
+__global__ void k_unpack(const cx<T>* __restrict__ r, cx<T>* __restrict__ b, int n0l, int n1l,
+                         int p1, int M, long long total)
+{
+    const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= total) return;
+    const int m = (int)(o % M);
+    const long long rest = o / M;
+    const int y = (int)(rest % ((long long)p1 * n1l));
+    const int i0 = (int)(rest / ((long long)p1 * n1l));
+    const int j = y / n1l;
+    const int i1 = y - j * n1l;
+    b[o] = r[(((long long)j * n0l + i0) * n1l + i1) * M + m];
+}
+
+template <typename T>
+hipError_t launch_pack(const cx<T>* a, cx<T>* s, int n0l, int n1l, int p1, int M, hipStream_t st)
+{
+    const long long lines = (long long)n0l * n1l;
+    const long long total = lines * p1 * M;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, s,
+                       lines, p1, M, total);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_unpack(const cx<T>* r, cx<T>* b, int n0l, int n1l, int p1, int M, hipStream_t st)
+{
+    const long long total = (long long)n0l * n1l * p1 * M;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpack<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, r, b,
+                       n0l, n1l, p1, M, total);
+    return hipGetLastError();
+}
+
+__global__ void k_copy16(const uint4* __restrict__ a, uint4* __restrict__ b, long long n16)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (long long)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+__global__ void k_copy1(const unsigned char* __restrict__ a, unsigned char* __restrict__ b, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0 || src == dst) return hipSuccess;
+    const bool vec = ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0) && (bytes % 16 == 0);
+    if (vec) {
+        const long long n16 = (long long)(bytes / 16);
+        long long blocks = (n16 + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4*)src,
+                           (uint4*)dst, n16);
+    } else {
+        hipLaunchKernelGGL(k_copy1, dim3((unsigned)((bytes + 255) / 256)), dim3(256), 0, s,
+                           (const unsigned char*)src, (unsigned char*)dst, (long long)bytes);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_twiddles<float>(cx<float>*, int, hipStream_t);
+template hipError_t launch_twiddles<double>(cx<double>*, int, hipStream_t);
+template hipError_t launch_poisson<float>(cx<float>*, int, int, int, float, hipStream_t);
+template hipError_t launch_poisson<double>(cx<double>*, int, int, int, double, hipStream_t);
+template hipError_t launch_pack<float>(const cx<float>*, cx<float>*, int, int, int, int, hipStream_t);
+template hipError_t launch_pack<double>(const cx<double>*, cx<double>*, int, int, int, int, hipStream_t);
+template hipError_t launch_unpack<float>(const cx<float>*, cx<float>*, int, int, int, int, hipStream_t);
+template hipError_t launch_unpack<double>(const cx<double>*, cx<double>*, int, int, int, int,
+                                          hipStream_t);
+
+} // namespace mifft

@@ -1,0 +1,17 @@
+// aux_kernels.hpp -- host launchers of the auxiliary kernels.
+#pragma once
+
+#include "fft_engine.hpp"
+
+namespace mifft {
+
+template <typename T> hipError_t launch_twiddles(cx<T>* w, int n, hipStream_t s);
+template <typename T>
+hipError_t launch_poisson(cx<T>* u, int n0, int n1, int n2c, T scale, hipStream_t s);
+template <typename T>
+hipError_t launch_pack(const cx<T>* a, cx<T>* s, int n0l, int n1l, int p1, int M, hipStream_t st);
+template <typename T>
+hipError_t launch_unpack(const cx<T>* r, cx<T>* b, int n0l, int n1l, int p1, int M, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+} // namespace mifft

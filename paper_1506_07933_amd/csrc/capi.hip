@@ -1,0 +1,382 @@
+// capi.hip -- the extern "C" entry points declared in include/mifft.h.
+//
+// Every argument is checked on the host before the first HIP call, so the
+// argument errors are the same with or without a device.  Handles are kept
+// in a registry so a destroyed or foreign handle is reported as BADPLAN
+// instead of being dereferenced.
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+
+#include "aux_kernels.hpp"
+#include "plan.hpp"
+
+namespace mifft {
+const char* last_error_cstr();
+int batch_create(mifft_batch* out, int count, const int* dims, int kind, int prec, unsigned flags);
+int batch_execute(mifft_batch b, void* const* in, void* const* out, void* stream, bool graph);
+int batch_destroy(mifft_batch b);
+int tune_plan(Plan& plan);
+} // namespace mifft
+
+using namespace mifft;
+
+struct mifft_plan_s : public Plan {};
+
+static std::mutex g_live_mu;
+static std::set<const void*> g_live;
+
+static bool is_live(const void* p)
+{
+    std::lock_guard<std::mutex> g(g_live_mu);
+    return g_live.count(p) != 0;
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+static int check_device(int* dev)
+{
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1)
+        return set_error(MIFFT_ERR_DEVICE, "no HIP device available (%s)",
+                         e != hipSuccess ? hipGetErrorString(e) : "0 devices");
+    e = hipGetDevice(dev);
+    if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, *dev);
+    if (e != hipSuccess)
+        return set_error(MIFFT_ERR_DEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(MIFFT_ERR_DEVICE, "device %d is %s; this library is built for gfx950", *dev,
+                         prop.gcnArchName);
+    return MIFFT_OK;
+}
+
+static int validate_dims(int n0, int n1, int n2, int kind, int prec)
+{
+    if (kind != MIFFT_C2C && kind != MIFFT_R2C)
+        return set_error(MIFFT_ERR_INVALID, "kind %d is not MIFFT_C2C or MIFFT_R2C", kind);
+    if (prec != MIFFT_FP32 && prec != MIFFT_FP64)
+        return set_error(MIFFT_ERR_INVALID, "precision %d is not MIFFT_FP32 or MIFFT_FP64", prec);
+    const int n[3] = {n0, n1, n2};
+    for (int i = 0; i < 3; ++i)
+        if (n[i] < 1) return set_error(MIFFT_ERR_INVALID, "n%d = %d must be >= 1", i, n[i]);
+    for (int i = 0; i < 3; ++i)
+        if (!supported_length(n[i]))
+            return set_error(MIFFT_ERR_UNSUPPORTED,
+                             "n%d = %d: axis lengths must be <= 1024 with prime factors 2, 3, 5", i,
+                             n[i]);
+    if (kind == MIFFT_R2C && (n2 % 2 != 0))
+        return set_error(MIFFT_ERR_UNSUPPORTED, "R2C needs an even n2 (got %d)", n2);
+    return MIFFT_OK;
+}
+
+static int finish_plan(Plan* p, mifft_plan* out)
+{
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        delete p;
+        return set_error(MIFFT_ERR_DEVICE, "plan set-up: %s", hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        g_live.insert(p);
+    }
+    *out = static_cast<mifft_plan>(p);
+    return MIFFT_OK;
+}
+
+extern "C" {
+
+int mifft_plan_create(mifft_plan* out, int n0, int n1, int n2, int kind, int prec, unsigned flags)
+{
+    clear_error();
+    if (!out) return set_error(MIFFT_ERR_INVALID, "out is NULL");
+    int rc = validate_dims(n0, n1, n2, kind, prec);
+    if (rc) return rc;
+    if (flags & ~(unsigned)MIFFT_TUNE) return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    int dev = 0;
+    if ((rc = check_device(&dev))) return rc;
+    mifft_plan_s* p = new mifft_plan_s();
+    p->n0 = n0;
+    p->n1 = n1;
+    p->n2 = n2;
+    p->kind = kind;
+    p->prec = prec;
+    p->device = dev;
+    p->esz = prec == MIFFT_FP64 ? 16 : 8;
+    if ((rc = build_plan(*p, flags))) {
+        delete p;
+        return rc;
+    }
+    if ((flags & MIFFT_TUNE) && (rc = tune_plan(*p))) {
+        delete p;
+        return rc;
+    }
+    if (p->ws_bytes) {
+        hipError_t e = hipMalloc(&p->ws, p->ws_bytes);
+        if (e != hipSuccess) {
+            delete p;
+            return set_error(MIFFT_ERR_NOMEM, "workspace of %zu bytes: %s", p->ws_bytes,
+                             hipGetErrorString(e));
+        }
+    }
+    return finish_plan(p, out);
+}
+
+int mifft_plan_create_pencil(mifft_plan* out, int n0, int n1, int n2, int p0, int p1, int kind,
+                             int prec, unsigned flags)
+{
+    clear_error();
+    if (!out) return set_error(MIFFT_ERR_INVALID, "out is NULL");
+    if (kind != MIFFT_C2C && kind != MIFFT_R2C) return set_error(MIFFT_ERR_INVALID, "bad kind %d", kind);
+    if (prec != MIFFT_FP32 && prec != MIFFT_FP64)
+        return set_error(MIFFT_ERR_INVALID, "bad precision %d", prec);
+    if (n0 < 1 || n1 < 1 || n2 < 1 || p0 < 1 || p1 < 1)
+        return set_error(MIFFT_ERR_INVALID, "grid and process grid extents must be >= 1");
+    if (flags & ~(unsigned)MIFFT_TUNE) return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if (kind != MIFFT_C2C)
+        return set_error(MIFFT_ERR_UNSUPPORTED, "the pencil share stages are C2C only");
+    if (n0 % p0 || n1 % p1 || n2 % p1)
+        return set_error(MIFFT_ERR_UNSUPPORTED,
+                         "process grid %dx%d does not divide the %dx%dx%d grid evenly", p0, p1, n0,
+                         n1, n2);
+    if (!supported_length(n1) || !supported_length(n2))
+        return set_error(MIFFT_ERR_UNSUPPORTED,
+                         "pencil axes n1 = %d, n2 = %d must be <= 1024 with prime factors 2, 3, 5",
+                         n1, n2);
+    if ((long long)(n0 / p0) * (n1 / p1) >= (1LL << 31))
+        return set_error(MIFFT_ERR_UNSUPPORTED, "share too large");
+    int dev = 0, rc;
+    if ((rc = check_device(&dev))) return rc;
+    mifft_plan_s* p = new mifft_plan_s();
+    p->n0 = n0;
+    p->n1 = n1;
+    p->n2 = n2;
+    p->p0 = p0;
+    p->p1 = p1;
+    p->pencil = true;
+    p->kind = kind;
+    p->prec = prec;
+    p->device = dev;
+    p->esz = prec == MIFFT_FP64 ? 16 : 8;
+    if ((rc = build_pencil(*p, flags))) {
+        delete p;
+        return rc;
+    }
+    return finish_plan(p, out);
+}
+
+int mifft_plan_destroy(mifft_plan plan)
+{
+    clear_error();
+    if (!plan) return MIFFT_OK;
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        if (!g_live.erase(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
+    }
+    delete static_cast<mifft_plan_s*>(plan);
+    return MIFFT_OK;
+}
+
+const char* mifft_last_error(void) { return last_error_cstr(); }
+
+size_t mifft_workspace_bytes(mifft_plan plan)
+{
+    if (!plan || !is_live(plan)) return 0;
+    return plan->pencil ? 0 : plan->ws_bytes;
+}
+
+size_t mifft_poisson_ws_bytes(mifft_plan plan)
+{
+    if (!plan || !is_live(plan)) return 0;
+    return plan->poisson_ws_bytes;
+}
+
+static int run_passes(const Plan& p, const std::vector<Pass>& list, const void* in, void* out,
+                      void* ws, void* send, void* recv, hipStream_t s)
+{
+    for (const Pass& q : list) {
+        auto res = [&](BufId b) -> void* {
+            switch (b) {
+            case B_IN: return const_cast<void*>(in);
+            case B_OUT: return out;
+            case B_WS: return ws;
+            case B_SEND: return send;
+            case B_RECV: return recv;
+            default: return nullptr;
+            }
+        };
+        hipError_t e = launch_pass(q, p.prec, res(q.src), res(q.dst), s);
+        if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    return MIFFT_OK;
+}
+
+static int check_exec(mifft_plan plan, const void* in, void* out, void* ws, bool use_ws)
+{
+    if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
+    if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
+    if (plan->pencil)
+        return set_error(MIFFT_ERR_BADPLAN, "pencil plans run through mifft_execute_pencil_stages");
+    if (!in || !out) return set_error(MIFFT_ERR_INVALID, "in / out must not be NULL");
+    if (!aligned16(in) || !aligned16(out))
+        return set_error(MIFFT_ERR_INVALID, "in / out must be 16-byte aligned");
+    if (use_ws && plan->ws_bytes && !ws)
+        return set_error(MIFFT_ERR_INVALID, "this plan needs %zu bytes of workspace", plan->ws_bytes);
+    if (use_ws && ws && !aligned16(ws)) return set_error(MIFFT_ERR_INVALID, "ws must be 16-byte aligned");
+    if (plan->kind == MIFFT_R2C && in == out)
+        return set_error(MIFFT_ERR_INVALID, "R2C / C2R must be out of place");
+    return MIFFT_OK;
+}
+
+int mifft_execute_forward_ws(mifft_plan plan, const void* in, void* out, void* ws, void* stream)
+{
+    clear_error();
+    int rc = check_exec(plan, in, out, ws, true);
+    if (rc) return rc;
+    return run_passes(*plan, plan->fwd, in, out, ws, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int mifft_execute_inverse_ws(mifft_plan plan, const void* in, void* out, void* ws, void* stream)
+{
+    clear_error();
+    int rc = check_exec(plan, in, out, ws, true);
+    if (rc) return rc;
+    return run_passes(*plan, plan->inv, in, out, ws, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int mifft_execute_forward(mifft_plan plan, const void* in, void* out, void* stream)
+{
+    clear_error();
+    int rc = check_exec(plan, in, out, nullptr, false);
+    if (rc) return rc;
+    return run_passes(*plan, plan->fwd, in, out, plan->ws, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int mifft_execute_inverse(mifft_plan plan, const void* in, void* out, void* stream)
+{
+    clear_error();
+    int rc = check_exec(plan, in, out, nullptr, false);
+    if (rc) return rc;
+    return run_passes(*plan, plan->inv, in, out, plan->ws, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void* stream)
+{
+    clear_error();
+    if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
+    if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
+    if (plan->pencil || plan->kind != MIFFT_R2C)
+        return set_error(MIFFT_ERR_BADPLAN, "the Poisson solve needs an R2C plan");
+    if (!f || !u) return set_error(MIFFT_ERR_INVALID, "f / u must not be NULL");
+    if (!aligned16(f) || !aligned16(u) || (ws && !aligned16(ws)))
+        return set_error(MIFFT_ERR_INVALID, "pointers must be 16-byte aligned");
+    if (f == u) return set_error(MIFFT_ERR_INVALID, "f and u must not overlap");
+    void* w = ws ? ws : plan->ws;
+    return run_passes(*plan, plan->poisson, f, u, w, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int mifft_execute_pencil_stages(mifft_plan plan, unsigned mask, void* a, void* send, void* recv,
+                                void* out, void* stream)
+{
+    clear_error();
+    if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
+    if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
+    if (!plan->pencil) return set_error(MIFFT_ERR_BADPLAN, "not a pencil plan");
+    const unsigned all = MIFFT_STAGE_Z | MIFFT_STAGE_PACK | MIFFT_STAGE_UNPACK | MIFFT_STAGE_Y;
+    if (mask == 0 || (mask & ~all)) return set_error(MIFFT_ERR_INVALID, "bad stage mask 0x%x", mask);
+    const bool z = mask & MIFFT_STAGE_Z, pk = mask & MIFFT_STAGE_PACK;
+    const bool up = mask & MIFFT_STAGE_UNPACK, y = mask & MIFFT_STAGE_Y;
+    auto need = [](const void* p, const char* name) {
+        if (!p) return set_error(MIFFT_ERR_INVALID, "%s must not be NULL for the selected stages", name);
+        if (!aligned16(p)) return set_error(MIFFT_ERR_INVALID, "%s must be 16-byte aligned", name);
+        return (int)MIFFT_OK;
+    };
+    int rc;
+    if ((z || pk) && (rc = need(a, "in"))) return rc;
+    if (pk && (rc = need(send, "sendbuf"))) return rc;
+    if (up && (rc = need(recv, "recvbuf"))) return rc;
+    if ((up || y) && (rc = need(out, "out"))) return rc;
+    std::vector<Pass> list;
+    if (z && pk)
+        list.push_back(plan->pz_pack);
+    else if (z)
+        list.push_back(plan->pz);
+    else if (pk)
+        list.push_back(plan->pk);
+    if (up && y)
+        list.push_back(plan->py_split);
+    else if (up)
+        list.push_back(plan->upk);
+    else if (y)
+        list.push_back(plan->py);
+    return run_passes(*plan, list, a, out, nullptr, send, recv, (hipStream_t)stream);
+}
+
+int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
+{
+    clear_error();
+    if (!plan || !buf || len == 0) return set_error(MIFFT_ERR_INVALID, "NULL argument");
+    if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
+    static const char* kn[] = {"contig", "contig_pack", "strided", "strided_unpack", "r2c_z",
+                               "c2r_z",  "poisson",     "pack",    "unpack",         "copy"};
+    std::string s;
+    auto add = [&](const char* tag, const Pass& q) {
+        char line[320];
+        int pol = q.vidx >= 0 ? variant_policy(plan->prec, q.vidx) : -1;
+        int tpl = q.vidx >= 0 ? variant_tpl(plan->prec, q.vidx) : 0;
+        snprintf(line, sizeof(line),
+                 "%s kind=%s L=%d policy=%d tpl=%d sgn=%d lines=%lld lpw=%d B=%d cols=%d groups=%d "
+                 "es=%lld grid=%u block=%u lds=%zu\n",
+                 tag, kn[q.kind], q.L, pol, tpl, q.sgn, q.nlines, q.lines_per_wg, q.B, q.cols,
+                 q.groups, q.es_in, q.grid, q.block, q.shmem);
+        s += line;
+    };
+    if (plan->pencil) {
+        add("pencil_z", plan->pz);
+        add("pencil_z_pack", plan->pz_pack);
+        add("pencil_pack", plan->pk);
+        add("pencil_unpack", plan->upk);
+        add("pencil_y", plan->py);
+        add("pencil_unpack_y", plan->py_split);
+    } else {
+        for (const Pass& q : plan->fwd) add("forward", q);
+        for (const Pass& q : plan->inv) add("inverse", q);
+    }
+    snprintf(buf, len, "%s", s.c_str());
+    return MIFFT_OK;
+}
+
+const char* mifft_version(void) { return "mifft 0.1 (gfx950)"; }
+
+int mifft_batch_create(mifft_batch* out, int count, const int* dims, int kind, int prec, unsigned flags)
+{
+    clear_error();
+    return batch_create(out, count, dims, kind, prec, flags);
+}
+
+int mifft_batch_execute_forward(mifft_batch batch, void* const* in, void* const* out, void* stream)
+{
+    clear_error();
+    return batch_execute(batch, in, out, stream, false);
+}
+
+int mifft_batch_graph_launch(mifft_batch batch, void* const* in, void* const* out, void* stream)
+{
+    clear_error();
+    return batch_execute(batch, in, out, stream, true);
+}
+
+int mifft_batch_destroy(mifft_batch batch)
+{
+    clear_error();
+    return batch_destroy(batch);
+}
+
+} // extern "C"

@@ -1,0 +1,342 @@
+// kernels.hpp -- the HIP kernels of the local FFT passes (templates).
+//
+// k_contig   batched 1-D FFTs along the contiguous axis (the z-pass,
+//            Algorithm 1 step 1), several lines per workgroup.  With
+//            OUT_PACK the stores go straight to the row all-to-all send
+//            layout S[j][i0][i1][m] (Sec. 2: pack before the exchange).
+// k_strided  batched 1-D FFTs along a strided axis (the y- and x-passes,
+//            Algorithm 1 steps 3 and 5).  A workgroup owns a tile of B
+//            adjacent columns, so every global access of a line element is a
+//            run of B contiguous complex values.  With IN_SPLIT the loads
+//            follow the unpack map of the receive layout (Sec. 2: unpack after
+//            the exchange), which fuses the unpack into the y-pass.
+// k_r2c_z    real z-lines: n2 reals are read as n2/2 complex values, FFT'd,
+//            and post-processed into the n2/2+1 outputs of the real DFT.
+// k_c2r_z    the inverse: pre-processing of the n2/2+1 inputs (imaginary
+//            parts of k2 = 0 and n2/2 discarded), half-length inverse FFT,
+//            de-interleave into n2 reals.
+#pragma once
+
+#include "fft_engine.hpp"
+
+namespace mifft {
+
+// ------------------------------------------------------------- contexts
+
+template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
+    using V = cx<T>;
+    static constexpr bool kSyncAfterFirstRead = false;
+    const V* __restrict__ in;
+    V* __restrict__ out;
+    V* lds;
+    const V* __restrict__ twd;
+    int t;
+    bool valid;
+    T sgn;           // +1 forward, -1 inverse (conjugate on load and store)
+    FastDiv pm;      // pack: block length M
+    long long pblk;  // pack: distance between send blocks
+
+    __device__ __forceinline__ V gload(int idx) const
+    {
+        V v = valid ? in[idx] : V{T(0), T(0)};
+        v.y *= sgn;
+        return v;
+    }
+    __device__ __forceinline__ V lds_get(int idx) const { return lds[lds_pad(idx)]; }
+    __device__ __forceinline__ void lds_put(int idx, V v) { lds[lds_pad(idx)] = v; }
+    __device__ __forceinline__ void final_put(int idx, V v)
+    {
+        if (!valid) return;
+        v.y *= sgn;
+        if constexpr (OUT_PACK) {
+            uint32_t q = fdiv((uint32_t)idx, pm);
+            out[(long long)q * pblk + (idx - (int)(q * pm.d))] = v;
+        } else {
+            out[idx] = v;
+        }
+    }
+    __device__ __forceinline__ V tw(int e) const { return twd[e]; }
+    __device__ __forceinline__ void sync() const
+    {
+        if constexpr (WAVE_LOCAL)
+            wave_sync();
+        else
+            __syncthreads();
+    }
+};
+
+template <typename T, bool IN_SPLIT> struct StridedCtx {
+    using V = cx<T>;
+    static constexpr bool kSyncAfterFirstRead = false;
+    const V* __restrict__ in;
+    V* __restrict__ out;
+    V* lds; // column c of the tile: element idx at lds[idx * B]
+    const V* __restrict__ twd;
+    int t;
+    int B;
+    bool valid;
+    T sgn;
+    long long es_in, es_out; // element strides
+    FastDiv split;           // IN_SPLIT: y = q * split.d + rem, address q * s_hi + rem * es_in
+    long long s_hi;
+
+    __device__ __forceinline__ V gload(int idx) const
+    {
+        V v{T(0), T(0)};
+        if (valid) {
+            if constexpr (IN_SPLIT) {
+                uint32_t q = fdiv((uint32_t)idx, split);
+                v = in[(long long)q * s_hi + (long long)(idx - (int)(q * split.d)) * es_in];
+            } else {
+                v = in[(long long)idx * es_in];
+            }
+        }
+        v.y *= sgn;
+        return v;
+    }
+    __device__ __forceinline__ V lds_get(int idx) const { return lds[idx * B]; }
+    __device__ __forceinline__ void lds_put(int idx, V v) { lds[idx * B] = v; }
+    __device__ __forceinline__ void final_put(int idx, V v)
+    {
+        if (!valid) return;
+        v.y *= sgn;
+        out[(long long)idx * es_out] = v;
+    }
+    __device__ __forceinline__ V tw(int e) const { return twd[e]; }
+    __device__ __forceinline__ void sync() const { __syncthreads(); }
+};
+
+// R2C z-line: reads complex pairs of the real line, leaves Z in LDS.
+template <typename T, bool WAVE_LOCAL> struct R2CCtx {
+    using V = cx<T>;
+    static constexpr bool kSyncAfterFirstRead = false;
+    const V* __restrict__ in;
+    V* lds;
+    const V* __restrict__ twd;
+    int t;
+    bool valid;
+    __device__ __forceinline__ V gload(int idx) const { return valid ? in[idx] : V{T(0), T(0)}; }
+    __device__ __forceinline__ V lds_get(int idx) const { return lds[lds_pad(idx)]; }
+    __device__ __forceinline__ void lds_put(int idx, V v) { lds[lds_pad(idx)] = v; }
+    __device__ __forceinline__ void final_put(int idx, V v) { lds[lds_pad(idx)] = v; }
+    __device__ __forceinline__ V tw(int e) const { return twd[e]; }
+    __device__ __forceinline__ void sync() const
+    {
+        if constexpr (WAVE_LOCAL)
+            wave_sync();
+        else
+            __syncthreads();
+    }
+};
+
+// C2R z-line: the first stage reads the pre-processed (and conjugated)
+// half-length input from the line staged in LDS.
+template <typename T, bool WAVE_LOCAL> struct C2RCtx {
+    using V = cx<T>;
+    static constexpr bool kSyncAfterFirstRead = true;
+    V* __restrict__ out; // the n2 reals of the line, as n2/2 pairs
+    V* lds;
+    const V* __restrict__ twd;  // twiddles of the half length M
+    const V* __restrict__ twd2; // exp(-2 pi i k / n2), k = 0 .. M
+    int t;
+    int M;
+    bool valid;
+
+    __device__ __forceinline__ V gload(int k) const
+    {
+        V z;
+        if (k == 0) {
+            T a = lds[lds_pad(0)].x, b = lds[lds_pad(M)].x;
+            z = V{a + b, a - b};
+        } else {
+            V a = lds[lds_pad(k)];
+            V b = cconj(lds[lds_pad(M - k)]);
+            V s = cadd(a, b);
+            V d = cmul(csub(a, b), cconj(twd2[k])); // (a - b) exp(+2 pi i k / n2)
+            z = V{s.x - d.y, s.y + d.x};            // s + i d
+        }
+        return cconj(z);
+    }
+    __device__ __forceinline__ V lds_get(int idx) const { return lds[lds_pad(idx)]; }
+    __device__ __forceinline__ void lds_put(int idx, V v) { lds[lds_pad(idx)] = v; }
+    __device__ __forceinline__ void final_put(int idx, V v)
+    {
+        if (valid) out[idx] = cconj(v);
+    }
+    __device__ __forceinline__ V tw(int e) const { return twd[e]; }
+    __device__ __forceinline__ void sync() const
+    {
+        if constexpr (WAVE_LOCAL)
+            wave_sync();
+        else
+            __syncthreads();
+    }
+};
+
+// A length-1 "FFT" is the identity.
+template <typename T, int TPL, typename Ctx> struct LineFFT<T, 1, TPL, Ctx, RadixList<>> {
+    __device__ __forceinline__ static void run(Ctx& c)
+    {
+        cx<T> v{T(0), T(0)};
+        if (c.t == 0) v = c.gload(0);
+        if constexpr (Ctx::kSyncAfterFirstRead) c.sync();
+        if (c.t == 0) c.final_put(0, v);
+    }
+};
+
+template <int L, int P> struct RL { using type = radix_list_t<L, P>; };
+template <int P> struct RL<1, P> { using type = RadixList<>; };
+
+template <int L, int TPL> constexpr bool wave_local() { return TPL <= 64 && (64 % TPL) == 0; }
+
+// ---------------------------------------------------------------- kernels
+
+template <typename T> struct ContigArgs {
+    const cx<T>* in;
+    cx<T>* out;
+    const cx<T>* tw;
+    int nlines;
+    int lines_per_wg;
+    T sgn;
+    FastDiv pm;
+    long long pblk;
+};
+
+template <typename T, int L, int P, int TPL, bool OUT_PACK>
+__global__ __launch_bounds__(1024) void k_contig(ContigArgs<T> a)
+{
+    using V = cx<T>;
+    constexpr bool WL = wave_local<L, TPL>();
+    extern __shared__ unsigned char smem_raw[];
+    V* smem = reinterpret_cast<V*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int ln = tid / TPL;
+    const long long line = (long long)blockIdx.x * a.lines_per_wg + ln;
+    ContigCtx<T, WL, OUT_PACK> c;
+    c.valid = line < a.nlines;
+    c.in = a.in + line * L;
+    if constexpr (OUT_PACK)
+        c.out = a.out + line * (long long)a.pm.d;
+    else
+        c.out = a.out + line * L;
+    c.lds = smem + ln * lds_padded_len(L);
+    c.twd = a.tw;
+    c.t = tid - ln * TPL;
+    c.sgn = a.sgn;
+    c.pm = a.pm;
+    c.pblk = a.pblk;
+    LineFFT<T, L, TPL, decltype(c), typename RL<L, P>::type>::run(c);
+}
+
+template <typename T> struct StridedArgs {
+    const cx<T>* in;
+    cx<T>* out;
+    const cx<T>* tw;
+    int B;
+    int log2B;
+    int cols;            // columns per group
+    int tiles_per_group; // ceil(cols / B)
+    long long gs_in, gs_out; // group strides
+    long long es_in, es_out; // element strides
+    T sgn;
+    FastDiv split;
+    long long s_hi;
+};
+
+template <typename T, int L, int P, int TPL, bool IN_SPLIT>
+__global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
+{
+    using V = cx<T>;
+    extern __shared__ unsigned char smem_raw[];
+    V* smem = reinterpret_cast<V*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int cc = tid & (a.B - 1);
+    const int t = tid >> a.log2B;
+    const int tile = blockIdx.x;
+    const int g = tile / a.tiles_per_group;
+    const int cb = tile - g * a.tiles_per_group;
+    const int col = cb * a.B + cc;
+    StridedCtx<T, IN_SPLIT> c;
+    c.valid = col < a.cols;
+    c.in = a.in + (long long)g * a.gs_in + col;
+    c.out = a.out + (long long)g * a.gs_out + col;
+    c.lds = smem + cc;
+    c.twd = a.tw;
+    c.t = t;
+    c.B = a.B;
+    c.sgn = a.sgn;
+    c.es_in = a.es_in;
+    c.es_out = a.es_out;
+    c.split = a.split;
+    c.s_hi = a.s_hi;
+    LineFFT<T, L, TPL, decltype(c), typename RL<L, P>::type>::run(c);
+}
+
+template <typename T> struct RealArgs {
+    const void* in;
+    void* out;
+    const cx<T>* tw;  // half-length twiddles
+    const cx<T>* tw2; // exp(-2 pi i k / n2)
+    int nlines;
+    int lines_per_wg;
+};
+
+// L = M = n2 / 2.
+template <typename T, int L, int P, int TPL>
+__global__ __launch_bounds__(1024) void k_r2c_z(RealArgs<T> a)
+{
+    using V = cx<T>;
+    constexpr bool WL = wave_local<L, TPL>();
+    extern __shared__ unsigned char smem_raw[];
+    V* smem = reinterpret_cast<V*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int ln = tid / TPL;
+    const long long line = (long long)blockIdx.x * a.lines_per_wg + ln;
+    R2CCtx<T, WL> c;
+    c.valid = line < a.nlines;
+    c.in = reinterpret_cast<const V*>(a.in) + line * L;
+    c.lds = smem + ln * lds_padded_len(L + 1);
+    c.twd = a.tw;
+    c.t = tid - ln * TPL;
+    LineFFT<T, L, TPL, decltype(c), typename RL<L, P>::type>::run(c);
+    c.sync();
+    if (!c.valid) return;
+    // X[k] = (a + b)/2 - (i/2) w^k (a - b),  a = Z[k mod M], b = conj(Z[(M - k) mod M])
+    V* out = reinterpret_cast<V*>(a.out) + line * (L + 1);
+    const T half = T(0.5);
+    for (int k = c.t; k <= L; k += TPL) {
+        V za = c.lds[lds_pad(k == L ? 0 : k)];
+        V zb = cconj(c.lds[lds_pad(k == 0 ? 0 : L - k)]);
+        V s = cadd(za, zb);
+        V p = cmul(a.tw2[k], csub(za, zb));
+        out[k] = V{half * (s.x + p.y), half * (s.y - p.x)};
+    }
+}
+
+template <typename T, int L, int P, int TPL>
+__global__ __launch_bounds__(1024) void k_c2r_z(RealArgs<T> a)
+{
+    using V = cx<T>;
+    constexpr bool WL = wave_local<L, TPL>();
+    extern __shared__ unsigned char smem_raw[];
+    V* smem = reinterpret_cast<V*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int ln = tid / TPL;
+    const long long line = (long long)blockIdx.x * a.lines_per_wg + ln;
+    C2RCtx<T, WL> c;
+    c.valid = line < a.nlines;
+    c.lds = smem + ln * lds_padded_len(L + 1);
+    c.twd = a.tw;
+    c.twd2 = a.tw2;
+    c.t = tid - ln * TPL;
+    c.M = L;
+    c.out = reinterpret_cast<V*>(a.out) + line * L;
+    if (c.valid) {
+        const V* in = reinterpret_cast<const V*>(a.in) + line * (L + 1);
+        for (int k = c.t; k <= L; k += TPL) c.lds[lds_pad(k)] = in[k];
+    }
+    c.sync();
+    LineFFT<T, L, TPL, decltype(c), typename RL<L, P>::type>::run(c);
+}
+
+} // namespace mifft

@@ -1,0 +1,112 @@
+// plan.hpp -- host-side plan: the pass list of one transform and its launch
+// geometry, shared by the single-transform C ABI and the batched executor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mifft.h"
+#include "registry.hpp"
+
+namespace mifft {
+
+enum PassKind {
+    P_CONTIG = 0,
+    P_CONTIG_PACK,
+    P_STRIDED,
+    P_STRIDED_SPLIT,
+    P_R2C,
+    P_C2R,
+    P_POISSON,
+    P_PACK,
+    P_UNPACK,
+    P_COPY
+};
+
+// Which caller buffer a pass reads or writes; resolved at execute time.
+enum BufId { B_NONE = 0, B_IN, B_OUT, B_WS, B_SEND, B_RECV };
+
+struct Pass {
+    PassKind kind = P_COPY;
+    int L = 1;
+    int vidx = -1; // index into the variant table of the plan's precision
+    BufId src = B_NONE, dst = B_NONE;
+    int sgn = 1;   // +1 forward, -1 inverse
+    // contiguous / real passes
+    long long nlines = 0;
+    int lines_per_wg = 1;
+    // strided passes
+    int B = 1, log2B = 0, cols = 0, tiles_per_group = 0, groups = 0;
+    long long gs_in = 0, gs_out = 0, es_in = 0, es_out = 0;
+    // pack / split
+    FastDiv fd{1, 1ull << 32};
+    long long blk = 0;
+    // auxiliary kernels
+    int n0 = 0, n1 = 0, n2c = 0, p1 = 0, M = 0;
+    size_t bytes = 0;
+    double scale = 1.0;
+    // launch geometry
+    unsigned grid = 0, block = 0;
+    size_t shmem = 0;
+    const void* tw = nullptr;
+    const void* tw2 = nullptr;
+};
+
+struct TuneChoice {
+    int contig = -1; // variant index per axis kind, -1 = heuristic
+    int strided = -1;
+};
+
+class Plan {
+public:
+    int n0 = 1, n1 = 1, n2 = 1, kind = MIFFT_C2C, prec = MIFFT_FP32;
+    bool pencil = false;
+    int p0 = 1, p1 = 1;
+    int device = 0;
+    size_t esz = 8; // bytes per complex element
+    std::vector<Pass> fwd, inv, poisson;
+    // pencil stages
+    Pass pz, pz_pack, pk, upk, py, py_split;
+    std::map<int, void*> twiddles; // length -> device table
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t poisson_ws_bytes = 0;
+
+    ~Plan();
+};
+
+// Status helpers (thread-local last error message).
+int set_error(int status, const char* fmt, ...);
+void clear_error();
+
+// Variant table access for the plan's precision.
+int variant_count(int prec);
+int variant_L(int prec, int idx);
+int variant_tpl(int prec, int idx);
+int variant_policy(int prec, int idx);
+int variant_emul(int prec, int idx);
+int find_variant(int prec, int L, int policy, int emul);
+int default_variant(int prec, int L);
+
+bool supported_length(int L);
+FastDiv make_fastdiv(uint32_t d);
+
+// Launch geometry heuristics.
+void set_contig_geometry(Pass& p, int prec, int tpl, int L, long long nlines, int lds_len);
+void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int groups, int forceB);
+
+// Enqueue one pass with resolved buffers.
+hipError_t launch_pass(const Pass& p, int prec, const void* src, void* dst, hipStream_t s);
+
+// Generate (or reuse) the twiddle table of length L on the current device.
+int get_twiddles(Plan& plan, int L, void** out);
+
+int build_plan(Plan& plan, unsigned flags);
+int build_pencil(Plan& plan, unsigned flags);
+
+} // namespace mifft

@@ -1,0 +1,32 @@
+// registry.hpp -- table of compiled kernel variants, per precision.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace mifft {
+
+template <typename T> using ContigFn = void (*)(ContigArgs<T>);
+template <typename T> using StridedFn = void (*)(StridedArgs<T>);
+template <typename T> using RealFn = void (*)(RealArgs<T>);
+
+// One compiled configuration of a line length: its radix policy, the
+// elements-per-thread multiplier and the kernels built from it.
+template <typename T> struct Variant {
+    int L;
+    int policy;
+    int emul;
+    int tpl;     // threads per line
+    int nstages;
+    int radix[24];
+    ContigFn<T> contig;
+    ContigFn<T> contig_pack;
+    StridedFn<T> strided;
+    StridedFn<T> strided_split;
+    RealFn<T> r2c; // line of 2L reals
+    RealFn<T> c2r;
+};
+
+// All variants of this precision (concatenated over the compiled chunks).
+template <typename T> const Variant<T>* variant_table(int* count);
+
+} // namespace mifft

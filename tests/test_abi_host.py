@@ -1,0 +1,130 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/mifft.h declares, and rejects bad arguments with the
+documented status codes before it makes any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "mifft.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1506_07933_amd._lib import lib
+    return lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mifft_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("mifft_plan_create", "mifft_execute_forward", "mifft_execute_inverse",
+                 "mifft_plan_destroy", "mifft_last_error", "mifft_plan_create_pencil",
+                 "mifft_execute_pencil_stages", "mifft_batch_create",
+                 "mifft_batch_execute_forward", "mifft_poisson_solve"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_binding_signatures_cover_header():
+    from paper_1506_07933_amd._lib import SIGNATURES
+    assert sorted(SIGNATURES) == declared_functions()
+
+
+def _create(L, n0, n1, n2, kind=0, prec=0, flags=0):
+    h = ctypes.c_void_p()
+    rc = L.mifft_plan_create(ctypes.byref(h), n0, n1, n2, kind, prec, flags)
+    return rc, h
+
+
+@pytest.mark.parametrize("args,status", [
+    ((0, 4, 4), 1), ((4, -1, 4), 1), ((4, 4, 0), 1),
+    ((7, 4, 4), 2), ((4, 4, 11), 2), ((2048, 4, 4), 2), ((4, 1026, 4), 2),
+    ((4, 4, 49), 2),
+])
+def test_bad_sizes(L, args, status):
+    rc, h = _create(L, *args)
+    assert rc == status
+    assert h.value is None
+    assert L.mifft_last_error()
+
+
+def test_bad_enums_and_flags(L):
+    assert _create(L, 4, 4, 4, kind=2)[0] == 1
+    assert _create(L, 4, 4, 4, prec=7)[0] == 1
+    assert _create(L, 4, 4, 4, flags=0x80)[0] == 1
+    assert L.mifft_plan_create(None, 4, 4, 4, 0, 0, 0) == 1
+
+
+def test_r2c_needs_even_n2(L):
+    rc, _ = _create(L, 4, 4, 9, kind=1)
+    assert rc == 2
+    assert b"even" in L.mifft_last_error()
+
+
+def test_pencil_validation(L):
+    h = ctypes.c_void_p()
+    f = L.mifft_plan_create_pencil
+    assert f(ctypes.byref(h), 1024, 1024, 1024, 4, 3, 0, 0, 0) == 2   # 3 does not divide 1024
+    assert f(ctypes.byref(h), 1024, 1024, 1024, 0, 4, 0, 0, 0) == 1
+    assert f(ctypes.byref(h), 1024, 1024, 1024, 4, 4, 1, 0, 0) == 2   # R2C share not offered
+    assert f(None, 1024, 1024, 1024, 4, 4, 0, 0, 0) == 1
+
+
+def test_stale_and_null_handles(L):
+    bogus = ctypes.c_void_p(0x1234560)
+    assert L.mifft_plan_destroy(None) == 0
+    assert L.mifft_plan_destroy(bogus) == 5
+    buf = ctypes.c_void_p(0x10000)
+    assert L.mifft_execute_forward(None, buf, buf, None) == 1
+    assert L.mifft_execute_forward(bogus, buf, buf, None) == 5
+    assert L.mifft_execute_inverse(bogus, buf, buf, None) == 5
+    assert L.mifft_execute_pencil_stages(bogus, 1, buf, buf, buf, buf, None) == 5
+    assert L.mifft_poisson_solve(bogus, buf, buf, None, None) == 5
+    assert L.mifft_workspace_bytes(bogus) == 0
+    s = ctypes.create_string_buffer(64)
+    assert L.mifft_plan_describe(bogus, s, 64) == 5
+    assert L.mifft_batch_destroy(None) == 0
+
+
+def test_last_error_is_per_call(L):
+    _create(L, 7, 4, 4)
+    assert L.mifft_last_error()
+    L.mifft_plan_destroy(None)
+    assert L.mifft_last_error() == b""
+
+
+def test_no_device_reports_device_error(L):
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    rc, h = _create(L, 32, 32, 32)
+    assert rc == 4
+    assert h.value is None
+
+
+def test_binding_raises_typed_error():
+    from paper_1506_07933_amd.fft import MifftError, plan_create
+    with pytest.raises(MifftError) as e:
+        plan_create(7, 4, 4)
+    assert e.value.status_name == "MIFFT_ERR_UNSUPPORTED"
+
+
+def test_package_exports_load_the_library():
+    import paper_1506_07933_amd as pkg
+    assert pkg.Plan.__name__ == "Plan"
+    assert pkg.PencilPlan.__name__ == "PencilPlan"
+    assert issubclass(pkg.MifftError, RuntimeError)
+    from paper_1506_07933_amd import Plan  # noqa: F401

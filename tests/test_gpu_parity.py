@@ -1,0 +1,296 @@
+"""GPU parity: the HIP path, called through the C ABI binding, against the
+FP64 CPU oracle on the same seeded inputs.
+
+Bars (per result, rel-L2 over every stored output element): <= 1e-13 for
+FP64 plans and <= 5e-6 for FP32 plans.  FP32 results are compared with the
+oracle run on the FP32 inputs upcast exactly to FP64, so only the GPU's own
+arithmetic is measured.  Pack / unpack stages move bytes and are compared
+bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.brute import brute_dft3_at
+from paper_1506_07933_amd import synth
+from conftest import TOL, rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+def _smooth(n):
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+SMOOTH = [n for n in range(1, 1025) if _smooth(n)]
+DEV = "cuda:0"
+CDT = {"fp32": np.complex64, "fp64": np.complex128}
+RDT = {"fp32": np.float32, "fp64": np.float64}
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def report(name, err, tol):
+    print("  %-48s rel_l2=%.3e (bar %.0e)" % (name, err, tol), flush=True)
+    assert err <= tol, "%s: rel-L2 %.3e above %.0e" % (name, err, tol)
+
+
+# ---------------------------------------------------------------- C2C
+
+def test_cfg1_c2c_complex128_32cube():
+    """32^3 complex128, U[-1,1) seed 0: forward + inverse vs oracle and brute force."""
+    from paper_1506_07933_amd import Plan
+    x = synth.uniform_complex((32, 32, 32), np.complex128, seed=0)
+    p = Plan(x.shape, "c2c", "fp64")
+    X = host(p.forward(gpu(x)))
+    ref = oracle.fft3d_c2c(x, -1)
+    report("cfg1 forward vs oracle", rel_l2(X, ref), 1e-13)
+    rng = np.random.default_rng(1)
+    ks = np.stack([rng.integers(0, 32, 300) for _ in range(3)], axis=1)
+    report("cfg1 forward vs brute force (300 samples)",
+           rel_l2(X[ks[:, 0], ks[:, 1], ks[:, 2]], brute_dft3_at(x, ks, -1)), 1e-13)
+    xi = host(p.inverse(gpu(X)))
+    report("cfg1 inverse vs oracle", rel_l2(xi, oracle.fft3d_c2c(X, +1)), 1e-13)
+    report("cfg1 inverse(forward(x)) vs N x", rel_l2(xi, 32 ** 3 * x), 1e-13)
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_every_compiled_length(prec, axis):
+    """Each compiled length along each axis (x: strided, y: strided, z:
+    contiguous), with small ragged extents on the other two axes."""
+    from paper_1506_07933_amd import Plan
+    rng = np.random.default_rng(axis)
+    worst = 0.0
+    for L in SMOOTH:
+        shape = [3, 5, 2]
+        shape[axis] = L
+        x = (rng.uniform(-1, 1, shape) + 1j * rng.uniform(-1, 1, shape)).astype(CDT[prec])
+        p = Plan(shape, "c2c", prec)
+        X = host(p.forward(gpu(x)))
+        e1 = rel_l2(X, oracle.fft3d_c2c(x.astype(np.complex128), -1))
+        Xi = host(p.inverse(gpu(x)))
+        e2 = rel_l2(Xi, oracle.fft3d_c2c(x.astype(np.complex128), +1))
+        p.close()
+        worst = max(worst, e1, e2)
+        assert e1 <= TOL[prec] and e2 <= TOL[prec], (L, shape, e1, e2)
+    report("all %d lengths on axis %d (%s), worst" % (len(SMOOTH), axis, prec), worst, TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 3, 1), (2, 3, 5),
+                                   (6, 10, 15), (48, 64, 96), (100, 120, 144), (125, 125, 125),
+                                   (3, 1024, 2), (1024, 3, 2), (2, 2, 1024), (81, 243, 27)])
+def test_c2c_shapes(prec, shape):
+    from paper_1506_07933_amd import Plan
+    x = synth.uniform_complex(shape, CDT[prec], seed=5)
+    p = Plan(shape, "c2c", prec)
+    X = host(p.forward(gpu(x)))
+    x64 = x.astype(np.complex128)
+    report("c2c %s %s forward" % (prec, shape), rel_l2(X, oracle.fft3d_c2c(x64, -1)), TOL[prec])
+    xi = host(p.inverse(gpu(X)))
+    n = int(np.prod(shape))
+    report("c2c %s %s round trip" % (prec, shape), rel_l2(xi, n * x64), TOL[prec])
+    p.close()
+
+
+def test_c2c_512cube_fp32_full_size():
+    """The headline workload at full size: 512^3 complex64, U[-1,1) seed 0,
+    in the launch configuration the benchmark times."""
+    from paper_1506_07933_amd import Plan
+    x = synth.uniform_complex((512, 512, 512), np.complex64, seed=0)
+    p = Plan(x.shape, "c2c", "fp32")
+    xd = gpu(x)
+    yd = torch.empty_like(xd)
+    p.forward(xd, out=yd)
+    X = host(yd)
+    ref = oracle.fft3d_c2c(x.astype(np.complex128), -1)
+    report("512^3 fp32 forward vs oracle", rel_l2(X, ref), 5e-6)
+    del ref
+    p.inverse(yd, out=yd)
+    xi = host(yd)
+    report("512^3 fp32 round trip", rel_l2(xi, float(512 ** 3) * x.astype(np.complex128)), 5e-6)
+    p.close()
+
+
+def test_inplace_matches_out_of_place_and_repeats_bitwise():
+    from paper_1506_07933_amd import Plan
+    x = synth.uniform_complex((64, 96, 128), np.complex64, seed=3)
+    p = Plan(x.shape, "c2c", "fp32")
+    xd = gpu(x)
+    a = host(p.forward(xd))
+    b = host(p.forward(xd))
+    np.testing.assert_array_equal(a, b)            # no atomics: repeats are bitwise equal
+    np.testing.assert_array_equal(host(xd), x)     # out of place leaves the input alone
+    yd = xd.clone()
+    p.forward(yd, out=yd)
+    np.testing.assert_array_equal(host(yd), a)     # in place gives the same bits
+    p.close()
+
+
+def test_nondefault_stream():
+    from paper_1506_07933_amd import Plan
+    x = synth.uniform_complex((32, 64, 128), np.complex128, seed=4)
+    p = Plan(x.shape, "c2c", "fp64")
+    s = torch.cuda.Stream()
+    xd = gpu(x)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        yd = torch.empty_like(xd)
+        p.forward(xd, out=yd, stream=s)
+    s.synchronize()
+    report("fp64 on a side stream", rel_l2(host(yd), oracle.fft3d_c2c(x, -1)), 1e-13)
+    p.close()
+
+
+# ------------------------------------------------------------ R2C / C2R
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cfg2_r2c_c2r_256cube(prec):
+    """256^3 real N(0,1): R2C to 256x256x129, C2R back (x N)."""
+    from paper_1506_07933_amd import Plan
+    x = synth.normal_real((256, 256, 256), RDT[prec], seed=0)
+    p = Plan(x.shape, "r2c", prec)
+    xd = gpu(x)
+    Y = p.forward(xd)
+    assert tuple(Y.shape) == (256, 256, 129)
+    Yh = host(Y)
+    x64 = x.astype(np.float64)
+    report("cfg2 r2c %s" % prec, rel_l2(Yh, oracle.fft3d_r2c(x64)), TOL[prec])
+    xr = host(p.inverse(Y))
+    np.testing.assert_array_equal(host(Y), Yh)     # C2R preserves its input
+    report("cfg2 c2r(r2c(x)) %s" % prec, rel_l2(xr, 256 ** 3 * x64), TOL[prec])
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_r2c_c2r_every_half_length(prec):
+    """n2 = 2M for every compiled M up to 512, plus a non-Hermitian C2R input
+    (the imaginary parts at k2 = 0 and n2/2 must be discarded)."""
+    from paper_1506_07933_amd import Plan
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for m in [v for v in SMOOTH if v <= 512]:
+        shape = (3, 5, 2 * m)
+        x = rng.standard_normal(shape).astype(RDT[prec])
+        p = Plan(shape, "r2c", prec)
+        Y = host(p.forward(gpu(x)))
+        e1 = rel_l2(Y, oracle.fft3d_r2c(x.astype(np.float64)))
+        h = (3, 5, m + 1)
+        yn = (rng.standard_normal(h) + 1j * rng.standard_normal(h)).astype(CDT[prec])
+        xr = host(p.inverse(gpu(yn)))
+        e2 = rel_l2(xr, oracle.fft3d_c2r(yn.astype(np.complex128), 2 * m))
+        p.close()
+        worst = max(worst, e1, e2)
+        assert e1 <= TOL[prec] and e2 <= TOL[prec], (m, e1, e2)
+    report("r2c/c2r all half lengths (%s), worst" % prec, worst, TOL[prec])
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 2), (1, 1, 4), (2, 3, 2), (5, 1, 6), (64, 32, 48),
+                                   (100, 120, 144)])
+def test_r2c_small_and_uneven(shape):
+    from paper_1506_07933_amd import Plan
+    x = synth.normal_real(shape, np.float64, seed=2)
+    p = Plan(shape, "r2c", "fp64")
+    Y = p.forward(gpu(x))
+    report("r2c fp64 %s" % (shape,), rel_l2(host(Y), oracle.fft3d_r2c(x)), 1e-13)
+    xr = host(p.inverse(Y))
+    report("c2r fp64 %s round trip" % (shape,), rel_l2(xr, int(np.prod(shape)) * x), 1e-13)
+    p.close()
+
+
+# -------------------------------------------------------------- Poisson
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [64, 128])
+def test_poisson_solve(prec, n):
+    from paper_1506_07933_amd import Plan
+    f, (ks, amp, ph) = synth.poisson_rhs(n, seed=n, dtype=RDT[prec])
+    p = Plan((n, n, n), "r2c", prec)
+    u = host(p.poisson(gpu(f)))
+    report("poisson %s n=%d vs oracle" % (prec, n), rel_l2(u, oracle.poisson_solve(f.astype(np.float64))),
+           TOL[prec])
+    # the mode part against the closed form, on a noise-free right-hand side
+    f0 = synth.mode_sum(n, ks, amp, ph).astype(RDT[prec])
+    u0 = host(p.poisson(gpu(f0)))
+    ref = synth.mode_sum(n, ks, -amp / np.sum(ks * ks, axis=1), ph)
+    report("poisson %s n=%d vs closed form" % (prec, n), rel_l2(u0, ref),
+           1e-12 if prec == "fp64" else 5e-6)
+    p.close()
+
+
+# --------------------------------------------------------- pencil share
+
+def test_cfg3_pencil_share_fused_and_unfused():
+    """One rank's share of a 1024^3 C2C transform on a 4x4 grid: local
+    256x256x1024 complex64; z-FFT, pack, loopback, unpack, y-FFT."""
+    from paper_1506_07933_amd import PencilPlan
+    pp = PencilPlan((1024, 1024, 1024), (4, 4), "fp32")
+    a = synth.uniform_complex(pp.local_shape, np.complex64, seed=0)
+    ref = oracle.pencil_share_forward(a.astype(np.complex128), 4)
+    ad = gpu(a)
+    send = torch.empty(pp.send_shape, dtype=torch.complex64, device=DEV)
+    out = torch.empty(pp.out_shape, dtype=torch.complex64, device=DEV)
+    pp.forward_share(ad, send, out, fused=True)
+    fused = host(out)
+    report("cfg3 fused share vs oracle", rel_l2(fused, ref), 5e-6)
+    np.testing.assert_array_equal(host(ad), a)     # fused z+pack leaves A alone
+    out2 = torch.empty_like(out)
+    pp.forward_share(ad, send, out2, fused=False)
+    unfused = host(out2)
+    report("cfg3 unfused share vs oracle", rel_l2(unfused, ref), 5e-6)
+    np.testing.assert_array_equal(fused, unfused)  # same kernels' arithmetic, same bits
+    pp.close()
+
+
+def test_pack_unpack_bit_exact():
+    from paper_1506_07933_amd import PencilPlan
+    from paper_1506_07933_amd._lib import MIFFT_STAGE_PACK, MIFFT_STAGE_UNPACK
+    pp = PencilPlan((24, 40, 60), (2, 4), "fp64")
+    a = synth.uniform_complex(pp.local_shape, np.complex128, seed=9)
+    send = torch.empty(pp.send_shape, dtype=torch.complex128, device=DEV)
+    pp.stages(MIFFT_STAGE_PACK, a=gpu(a), send=send)
+    s = host(send)
+    np.testing.assert_array_equal(s, oracle.pencil_pack(a, 4))
+    r = synth.uniform_complex(pp.send_shape, np.complex128, seed=10)
+    out = torch.empty(pp.out_shape, dtype=torch.complex128, device=DEV)
+    pp.stages(MIFFT_STAGE_UNPACK, recv=gpu(r), out=out)
+    np.testing.assert_array_equal(host(out), oracle.pencil_unpack(r, pp.n1l))
+    pp.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_pencil_row_group_emulation(prec):
+    """All p1 = 4 ranks of one process row held on the GPU; the all-to-all is
+    done with device copies.  After the y-FFT rank j holds the k2 block j of
+    the 2-D (y, z) DFT of each x-slab."""
+    from paper_1506_07933_amd import PencilPlan
+    p1, N = 4, (8, 64, 96)
+    pp = PencilPlan(N, (1, p1), prec)
+    g = synth.uniform_complex((N[0], N[1], N[2]), CDT[prec], seed=7)
+    cd = torch.complex64 if prec == "fp32" else torch.complex128
+    sends = []
+    for r in range(p1):
+        share = gpu(g[:, r * pp.n1l:(r + 1) * pp.n1l, :])
+        s = torch.empty(pp.send_shape, dtype=cd, device=DEV)
+        pp.stages(1 | 2, a=share, send=s)
+        sends.append(s)
+    ref = oracle.fft_axis(oracle.fft_axis(g.astype(np.complex128), 2, -1), 1, -1)
+    for j in range(p1):
+        recv = torch.stack([sends[r][j] for r in range(p1)]).contiguous()
+        out = torch.empty(pp.out_shape, dtype=cd, device=DEV)
+        pp.stages(4 | 8, recv=recv, out=out)
+        report("row-group rank %d (%s)" % (j, prec), rel_l2(host(out), ref[:, :, j * pp.m:(j + 1) * pp.m]),
+               TOL[prec])
+    pp.close()
