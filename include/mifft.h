@@ -210,6 +210,20 @@ int mifft_batch_destroy(mifft_batch batch);
  */
 int mifft_plan_describe(mifft_plan plan, char* buf, size_t len);
 
+/*
+ * Per-pass timing for benchmarks (the per-phase breakdown of Sec. 3, Fig. 3e-f
+ * and Fig. 4, on the local phases).  mifft_profile_begin makes the next
+ * `max_calls` execute calls of this plan record a HIP event on their stream
+ * before the first pass and after every pass.  mifft_profile_end waits for
+ * those events, writes the mean duration in milliseconds of each pass of the
+ * most recent pass list (at most max_passes values) into avg_ms, their count
+ * into *npasses and the number of profiled calls into *ncalls, and stops
+ * recording.  Calls beyond max_calls are not recorded.  Event records cost a
+ * few microseconds per pass and are captured like any other stream work.
+ */
+int mifft_profile_begin(mifft_plan plan, int max_calls);
+int mifft_profile_end(mifft_plan plan, float* avg_ms, int max_passes, int* npasses, int* ncalls);
+
 /* Version string of the library build. */
 const char* mifft_version(void);
 

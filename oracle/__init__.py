@@ -67,11 +67,18 @@ def _load():
             lib.oracle_fft3d_r2c.argtypes = [dp, dp, ci, ci, ci]
             lib.oracle_fft3d_c2r.argtypes = [dp, dp, ci, ci, ci]
             lib.oracle_poisson_half.argtypes = [dp, ci, ci, ci, ctypes.c_double]
+            lib.oracle_max_threads.argtypes = []
+            lib.oracle_max_threads.restype = ci
             for f in (lib.oracle_fft1d, lib.oracle_fft3d_c2c, lib.oracle_fft_axis,
                       lib.oracle_fft3d_r2c, lib.oracle_fft3d_c2r, lib.oracle_poisson_half):
                 f.restype = None
             _lib = lib
     return _lib
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP loops use on this host."""
+    return int(_load().oracle_max_threads())
 
 
 def _dptr(a: np.ndarray):

@@ -205,6 +205,20 @@ static void fft_axis(cplx* a, int64_t outer, int len, int64_t inner, int sign)
 
 /* ---- exported entry points (called through ctypes by the test suite) ---- */
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of threads the OpenMP loops above will use. */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* 1-D transform of `batch` contiguous lines of length n, in place. */
 void oracle_fft1d(double* data, int64_t batch, int n, int sign)
 {

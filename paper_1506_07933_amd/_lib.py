@@ -40,6 +40,9 @@ SIGNATURES = {
     "mifft_batch_graph_launch": (_i, [_vp, _vpp, _vpp, _vp]),
     "mifft_batch_destroy": (_i, [_vp]),
     "mifft_plan_describe": (_i, [_vp, ctypes.c_char_p, _sz]),
+    "mifft_profile_begin": (_i, [_vp, _i]),
+    "mifft_profile_end": (_i, [_vp, ctypes.POINTER(ctypes.c_float), _i,
+                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "mifft_version": (ctypes.c_char_p, []),
 }
 

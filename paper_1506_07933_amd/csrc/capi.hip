@@ -4,6 +4,7 @@
 // argument errors are the same with or without a device.  Handles are kept
 // in a registry so a destroyed or foreign handle is reported as BADPLAN
 // instead of being dereferenced.
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -196,9 +197,18 @@ size_t mifft_poisson_ws_bytes(mifft_plan plan)
     return plan->poisson_ws_bytes;
 }
 
-static int run_passes(const Plan& p, const std::vector<Pass>& list, const void* in, void* out,
+static int run_passes(const Plan& cp, const std::vector<Pass>& list, const void* in, void* out,
                       void* ws, void* send, void* recv, hipStream_t s)
 {
+    Plan& p = const_cast<Plan&>(cp);
+    hipEvent_t* ev = nullptr;
+    if (p.prof_calls < p.prof_max_calls && (int)list.size() + 1 <= p.prof_stride) {
+        ev = &p.prof_events[(size_t)p.prof_calls * p.prof_stride];
+        p.prof_npass = (int)list.size();
+        ++p.prof_calls;
+        hipEventRecord(ev[0], s);
+    }
+    int qi = 0;
     for (const Pass& q : list) {
         auto res = [&](BufId b) -> void* {
             switch (b) {
@@ -212,6 +222,7 @@ static int run_passes(const Plan& p, const std::vector<Pass>& list, const void* 
         };
         hipError_t e = launch_pass(q, p.prec, res(q.src), res(q.dst), s);
         if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+        if (ev) hipEventRecord(ev[++qi], s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
@@ -317,6 +328,55 @@ int mifft_execute_pencil_stages(mifft_plan plan, unsigned mask, void* a, void* s
     else if (y)
         list.push_back(plan->py);
     return run_passes(*plan, list, a, out, nullptr, send, recv, (hipStream_t)stream);
+}
+
+int mifft_profile_begin(mifft_plan plan, int max_calls)
+{
+    clear_error();
+    if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
+    if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
+    if (max_calls < 1 || max_calls > 100000) return set_error(MIFFT_ERR_INVALID, "max_calls out of range");
+    size_t longest = std::max(plan->fwd.size(), std::max(plan->inv.size(), plan->poisson.size()));
+    if (longest < 2) longest = 2;
+    const int stride = (int)longest + 1;
+    const size_t need = (size_t)max_calls * stride;
+    while (plan->prof_events.size() < need) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(err));
+        plan->prof_events.push_back(e);
+    }
+    plan->prof_stride = stride;
+    plan->prof_max_calls = max_calls;
+    plan->prof_calls = 0;
+    plan->prof_npass = 0;
+    return MIFFT_OK;
+}
+
+int mifft_profile_end(mifft_plan plan, float* avg_ms, int max_passes, int* npasses, int* ncalls)
+{
+    clear_error();
+    if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
+    if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
+    if (!avg_ms || !npasses || !ncalls || max_passes < 1) return set_error(MIFFT_ERR_INVALID, "NULL output");
+    const int calls = plan->prof_calls, np = plan->prof_npass;
+    *ncalls = calls;
+    *npasses = np;
+    for (int i = 0; i < max_passes; ++i) avg_ms[i] = 0.f;
+    for (int c = 0; c < calls; ++c) {
+        hipEvent_t* ev = &plan->prof_events[(size_t)c * plan->prof_stride];
+        hipError_t err = hipEventSynchronize(ev[np]);
+        if (err != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "hipEventSynchronize: %s", hipGetErrorString(err));
+        for (int i = 0; i < np && i < max_passes; ++i) {
+            float ms = 0.f;
+            err = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            if (err != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "hipEventElapsedTime: %s", hipGetErrorString(err));
+            avg_ms[i] += ms / calls;
+        }
+    }
+    plan->prof_max_calls = 0;
+    plan->prof_calls = 0;
+    return MIFFT_OK;
 }
 
 int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)

@@ -302,6 +302,7 @@ int get_twiddles(Plan& plan, int L, void** out)
 
 Plan::~Plan()
 {
+    for (hipEvent_t e : prof_events) hipEventDestroy(e);
     for (auto& kv : twiddles) hipFree(kv.second);
     if (ws) hipFree(ws);
 }

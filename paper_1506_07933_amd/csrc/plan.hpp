@@ -76,6 +76,9 @@ public:
     void* ws = nullptr;
     size_t ws_bytes = 0;
     size_t poisson_ws_bytes = 0;
+    // opt-in per-pass event timing
+    std::vector<hipEvent_t> prof_events; // max_calls * (max passes + 1)
+    int prof_max_calls = 0, prof_calls = 0, prof_stride = 0, prof_npass = 0;
 
     ~Plan();
 };

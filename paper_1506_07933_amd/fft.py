@@ -103,6 +103,19 @@ def plan_describe(plan: int) -> str:
     return buf.value.decode()
 
 
+def profile_begin(plan: int, max_calls: int) -> None:
+    check(lib.mifft_profile_begin(plan, max_calls), "mifft_profile_begin")
+
+
+def profile_end(plan: int, max_passes: int = 16):
+    """Mean per-pass durations (ms) of the profiled calls, and the call count."""
+    buf = (ctypes.c_float * max_passes)()
+    npass, ncalls = ctypes.c_int(), ctypes.c_int()
+    check(lib.mifft_profile_end(plan, buf, max_passes, ctypes.byref(npass), ctypes.byref(ncalls)),
+          "mifft_profile_end")
+    return [float(buf[i]) for i in range(npass.value)], ncalls.value
+
+
 def version() -> str:
     return lib.mifft_version().decode()
 
@@ -246,4 +259,4 @@ class PencilPlan:
 __all__ = ["Plan", "PencilPlan", "MifftError", "plan_create", "plan_create_pencil",
            "execute_forward", "execute_inverse", "execute_forward_ws", "execute_inverse_ws",
            "execute_pencil_stages", "poisson_solve", "workspace_bytes", "poisson_ws_bytes",
-           "plan_destroy", "plan_describe", "version"]
+           "plan_destroy", "plan_describe", "profile_begin", "profile_end", "version"]

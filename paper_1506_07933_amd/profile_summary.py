@@ -1,0 +1,127 @@
+"""Summarise rocprofv3 output of bench.py runs into profiles/.
+
+    python -m paper_1506_07933_amd.profile_summary \
+        --trace gpurun_out/trace --fetch gpurun_out/pmc_fetch --write gpurun_out/pmc_write \
+        --copy-fetch gpurun_out/pmc_copy_fetch --copy-write gpurun_out/pmc_copy_write \
+        --passes z_contig,y_strided,x_strided --title "..." --command "..." --out profiles/x.md
+
+The kernel trace gives per-dispatch durations; dispatches of the transform's
+kernels are assigned to passes in launch order (the pass list repeats once per
+transform).  FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are scaled by what the
+same counters read for a plain device copy of known size (bench.py --mode
+copy), and the per-pass HBM bytes are written to profiles/traffic.json with a
+hash of the kernel sources, so the benchmark can drop them once the kernels
+change.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import statistics
+
+
+def _csv(d: str, suffix: str):
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise FileNotFoundError("no *%s under %s" % (suffix, d))
+    rows = []
+    for f in files:
+        rows += list(csv.DictReader(open(f)))
+    return rows
+
+
+def _fft_dispatches(rows, skip=("twiddles",)):
+    rows = [r for r in rows if not any(s in r["Kernel_Name"] for s in skip)]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    return rows
+
+
+def _per_pass(rows, npass):
+    groups = [[] for _ in range(npass)]
+    for i, r in enumerate(rows):
+        groups[i % npass].append(r)
+    return groups
+
+
+def copy_scale(fetch_dir, write_dir, copy_bytes=1 << 30):
+    f = [float(r["Counter_Value"]) for r in _csv(fetch_dir, "counter_collection.csv")
+         if "copyBuffer" in r["Kernel_Name"]]
+    w = [float(r["Counter_Value"]) for r in _csv(write_dir, "counter_collection.csv")
+         if "copyBuffer" in r["Kernel_Name"]]
+    kib = copy_bytes / 1024.0
+    return kib / statistics.mean(f), kib / statistics.mean(w), statistics.mean(f), statistics.mean(w)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--passes", required=True)
+    ap.add_argument("--alg-bytes", type=float, required=True, help="algorithmic bytes per pass")
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--counter-command", default="")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--traffic-json", default="")
+    a = ap.parse_args()
+    names = a.passes.split(",")
+    npass = len(names)
+
+    trace = _fft_dispatches(_csv(a.trace, "kernel_trace.csv"))
+    groups = _per_pass(trace, npass)
+    lines = ["# " + a.title, "", "Command (kernel trace):", "", "    " + a.command, ""]
+    lines += ["| pass | kernel | dispatches | mean us | min us | max us | alg GB/s (mean) |",
+              "|---|---|---|---|---|---|---|"]
+    summary = {}
+    for name, g in zip(names, groups):
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in g]
+        mean = statistics.mean(d)
+        kern = g[0]["Kernel_Name"].split("(")[0]
+        lines.append("| %s | `%s` | %d | %.1f | %.1f | %.1f | %.0f |" % (
+            name, kern, len(d), mean, min(d), max(d), a.alg_bytes / (mean * 1e-6) / 1e9))
+        summary[name] = {"kernel": kern, "mean_us": mean}
+    lines.append("")
+    traffic = {}
+    if a.fetch and a.write and a.copy_fetch and a.copy_write:
+        sf, sw, cf, cw = copy_scale(a.copy_fetch, a.copy_write)
+        fr = _per_pass(_fft_dispatches(_csv(a.fetch, "counter_collection.csv")), npass)
+        wr = _per_pass(_fft_dispatches(_csv(a.write, "counter_collection.csv")), npass)
+        lines += ["Counters (separate runs, `--pmc FETCH_SIZE` then `--pmc WRITE_SIZE`):", "",
+                  "    " + a.counter_command, "",
+                  "Scale: a plain 1 GiB device copy reads FETCH_SIZE = %.1f KiB and "
+                  "WRITE_SIZE = %.1f KiB, so FETCH_SIZE is multiplied by %.4f and WRITE_SIZE "
+                  "by %.4f." % (cf, cw, sf, sw), "",
+                  "| pass | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes / launch (scaled) | "
+                  "/ algorithmic |", "|---|---|---|---|---|"]
+        for name, f, w in zip(names, fr, wr):
+            fk = statistics.mean(float(r["Counter_Value"]) for r in f)
+            wk = statistics.mean(float(r["Counter_Value"]) for r in w)
+            hbm = (fk * sf + wk * sw) * 1024.0
+            traffic[name] = {"fetch_kib": fk, "write_kib": wk, "hbm_bytes_per_launch": hbm}
+            lines.append("| %s | %.1f | %.1f | %.4g | %.4f |" % (name, fk, wk, hbm, hbm / a.alg_bytes))
+        lines.append("")
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    if a.traffic_json and traffic:
+        here = os.path.dirname(os.path.abspath(__file__))
+        import sys
+        sys.path.insert(0, os.path.dirname(here))
+        from bench import csrc_hash
+        data = {}
+        if os.path.exists(a.traffic_json):
+            data = json.load(open(a.traffic_json))
+        if data.get("csrc_hash") != csrc_hash():
+            data = {"csrc_hash": csrc_hash(), "kernels": {}}
+        data["kernels"].update(traffic)
+        json.dump(data, open(a.traffic_json, "w"), indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
