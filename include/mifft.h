@@ -66,6 +66,10 @@ typedef enum {
                               uses, Sec. 3, Implementation Details); consults and
                               updates the wisdom file named by MIFFT_WISDOM */
 
+#define MIFFT_PLAN_ONLY 2u /* build the pass list without touching the device: the
+                              plan can be described (mifft_plan_describe) and
+                              destroyed, execute calls return MIFFT_ERR_BADPLAN */
+
 /* Longest axis a single-pass kernel handles. */
 #define MIFFT_MAX_AXIS 1024
 
@@ -84,7 +88,7 @@ typedef enum {
  *          R2C needs an even n2
  *   kind   MIFFT_C2C or MIFFT_R2C (the R2C plan runs C2R as its inverse)
  *   prec   MIFFT_FP32 (complex64 / float32) or MIFFT_FP64
- *   flags  MIFFT_HEURISTIC or MIFFT_TUNE
+ *   flags  MIFFT_HEURISTIC, MIFFT_TUNE or MIFFT_PLAN_ONLY
  * Allocates device twiddle tables (generated in FP64 on the GPU, rounded to
  * nearest for FP32 plans) and the default workspace on the current device.
  */

@@ -98,10 +98,15 @@ int mifft_plan_create(mifft_plan* out, int n0, int n1, int n2, int kind, int pre
     if (!out) return set_error(MIFFT_ERR_INVALID, "out is NULL");
     int rc = validate_dims(n0, n1, n2, kind, prec);
     if (rc) return rc;
-    if (flags & ~(unsigned)MIFFT_TUNE) return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if (flags & ~(unsigned)(MIFFT_TUNE | MIFFT_PLAN_ONLY))
+        return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    const bool plan_only = flags & MIFFT_PLAN_ONLY;
+    if (plan_only && (flags & MIFFT_TUNE))
+        return set_error(MIFFT_ERR_INVALID, "MIFFT_TUNE needs the device; it cannot be combined with MIFFT_PLAN_ONLY");
     int dev = 0;
-    if ((rc = check_device(&dev))) return rc;
+    if (!plan_only && (rc = check_device(&dev))) return rc;
     mifft_plan_s* p = new mifft_plan_s();
+    p->plan_only = plan_only;
     p->n0 = n0;
     p->n1 = n1;
     p->n2 = n2;
@@ -117,11 +122,17 @@ int mifft_plan_create(mifft_plan* out, int n0, int n1, int n2, int kind, int pre
         delete p;
         return rc;
     }
-    if (p->ws_bytes) {
-        hipError_t e = hipMalloc(&p->ws, p->ws_bytes);
+    if (plan_only) {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        g_live.insert(p);
+        *out = static_cast<mifft_plan>(p);
+        return MIFFT_OK;
+    }
+    if (p->default_ws_bytes) {
+        hipError_t e = hipMalloc(&p->ws, p->default_ws_bytes);
         if (e != hipSuccess) {
             delete p;
-            return set_error(MIFFT_ERR_NOMEM, "workspace of %zu bytes: %s", p->ws_bytes,
+            return set_error(MIFFT_ERR_NOMEM, "workspace of %zu bytes: %s", p->default_ws_bytes,
                              hipGetErrorString(e));
         }
     }
@@ -138,7 +149,8 @@ int mifft_plan_create_pencil(mifft_plan* out, int n0, int n1, int n2, int p0, in
         return set_error(MIFFT_ERR_INVALID, "bad precision %d", prec);
     if (n0 < 1 || n1 < 1 || n2 < 1 || p0 < 1 || p1 < 1)
         return set_error(MIFFT_ERR_INVALID, "grid and process grid extents must be >= 1");
-    if (flags & ~(unsigned)MIFFT_TUNE) return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if (flags & ~(unsigned)(MIFFT_TUNE | MIFFT_PLAN_ONLY))
+        return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
     if (kind != MIFFT_C2C)
         return set_error(MIFFT_ERR_UNSUPPORTED, "the pencil share stages are C2C only");
     if (n0 % p0 || n1 % p1 || n2 % p1)
@@ -152,8 +164,10 @@ int mifft_plan_create_pencil(mifft_plan* out, int n0, int n1, int n2, int p0, in
     if ((long long)(n0 / p0) * (n1 / p1) >= (1LL << 31))
         return set_error(MIFFT_ERR_UNSUPPORTED, "share too large");
     int dev = 0, rc;
-    if ((rc = check_device(&dev))) return rc;
+    const bool plan_only = flags & MIFFT_PLAN_ONLY;
+    if (!plan_only && (rc = check_device(&dev))) return rc;
     mifft_plan_s* p = new mifft_plan_s();
+    p->plan_only = plan_only;
     p->n0 = n0;
     p->n1 = n1;
     p->n2 = n2;
@@ -167,6 +181,12 @@ int mifft_plan_create_pencil(mifft_plan* out, int n0, int n1, int n2, int p0, in
     if ((rc = build_pencil(*p, flags))) {
         delete p;
         return rc;
+    }
+    if (plan_only) {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        g_live.insert(p);
+        *out = static_cast<mifft_plan>(p);
+        return MIFFT_OK;
     }
     return finish_plan(p, out);
 }
@@ -235,6 +255,7 @@ static int check_exec(mifft_plan plan, const void* in, void* out, void* ws, bool
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
     if (plan->pencil)
         return set_error(MIFFT_ERR_BADPLAN, "pencil plans run through mifft_execute_pencil_stages");
+    if (plan->plan_only) return set_error(MIFFT_ERR_BADPLAN, "plan was built with MIFFT_PLAN_ONLY");
     if (!in || !out) return set_error(MIFFT_ERR_INVALID, "in / out must not be NULL");
     if (!aligned16(in) || !aligned16(out))
         return set_error(MIFFT_ERR_INVALID, "in / out must be 16-byte aligned");
@@ -285,12 +306,14 @@ int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void*
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
     if (plan->pencil || plan->kind != MIFFT_R2C)
         return set_error(MIFFT_ERR_BADPLAN, "the Poisson solve needs an R2C plan");
+    if (plan->plan_only) return set_error(MIFFT_ERR_BADPLAN, "plan was built with MIFFT_PLAN_ONLY");
     if (!f || !u) return set_error(MIFFT_ERR_INVALID, "f / u must not be NULL");
     if (!aligned16(f) || !aligned16(u) || (ws && !aligned16(ws)))
         return set_error(MIFFT_ERR_INVALID, "pointers must be 16-byte aligned");
     if (f == u) return set_error(MIFFT_ERR_INVALID, "f and u must not overlap");
-    void* w = ws ? ws : plan->ws;
-    return run_passes(*plan, plan->poisson, f, u, w, nullptr, nullptr, (hipStream_t)stream);
+    char* w = (char*)(ws ? ws : plan->ws);
+    const size_t half = plan->poisson_ws_bytes / 2;
+    return run_passes(*plan, plan->poisson, f, u, nullptr, w, w + half, (hipStream_t)stream);
 }
 
 int mifft_execute_pencil_stages(mifft_plan plan, unsigned mask, void* a, void* send, void* recv,
@@ -300,6 +323,7 @@ int mifft_execute_pencil_stages(mifft_plan plan, unsigned mask, void* a, void* s
     if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
     if (!plan->pencil) return set_error(MIFFT_ERR_BADPLAN, "not a pencil plan");
+    if (plan->plan_only) return set_error(MIFFT_ERR_BADPLAN, "plan was built with MIFFT_PLAN_ONLY");
     const unsigned all = MIFFT_STAGE_Z | MIFFT_STAGE_PACK | MIFFT_STAGE_UNPACK | MIFFT_STAGE_Y;
     if (mask == 0 || (mask & ~all)) return set_error(MIFFT_ERR_INVALID, "bad stage mask 0x%x", mask);
     const bool z = mask & MIFFT_STAGE_Z, pk = mask & MIFFT_STAGE_PACK;
@@ -393,9 +417,9 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
         int tpl = q.vidx >= 0 ? variant_tpl(plan->prec, q.vidx) : 0;
         snprintf(line, sizeof(line),
                  "%s kind=%s L=%d policy=%d tpl=%d sgn=%d lines=%lld lpw=%d B=%d cols=%d groups=%d "
-                 "es=%lld grid=%u block=%u lds=%zu\n",
+                 "es=%lld/%lld gs=%lld/%lld grid=%u block=%u lds=%zu\n",
                  tag, kn[q.kind], q.L, pol, tpl, q.sgn, q.nlines, q.lines_per_wg, q.B, q.cols,
-                 q.groups, q.es_in, q.grid, q.block, q.shmem);
+                 q.groups, q.es_in, q.es_out, q.gs_in, q.gs_out, q.grid, q.block, q.shmem);
         s += line;
     };
     if (plan->pencil) {

@@ -191,6 +191,9 @@ template <int L, int TPL> constexpr bool wave_local() { return TPL <= 64 && (64 
 
 // ---------------------------------------------------------------- kernels
 
+// Line l of a batch sits at (l / ni) * s_o + (l % ni) * s_i on each side, so a
+// pass can read lines in one order and write them in another (the lines
+// themselves stay contiguous).
 template <typename T> struct ContigArgs {
     const cx<T>* in;
     cx<T>* out;
@@ -200,6 +203,8 @@ template <typename T> struct ContigArgs {
     T sgn;
     FastDiv pm;
     long long pblk;
+    int ni;
+    long long is_o, is_i, os_o, os_i;
 };
 
 template <typename T, int L, int P, int TPL, bool OUT_PACK>
@@ -214,11 +219,12 @@ __global__ __launch_bounds__(1024) void k_contig(ContigArgs<T> a)
     const long long line = (long long)blockIdx.x * a.lines_per_wg + ln;
     ContigCtx<T, WL, OUT_PACK> c;
     c.valid = line < a.nlines;
-    c.in = a.in + line * L;
+    const long long lo = line / a.ni, li = line - lo * a.ni;
+    c.in = a.in + lo * a.is_o + li * a.is_i;
     if constexpr (OUT_PACK)
         c.out = a.out + line * (long long)a.pm.d;
     else
-        c.out = a.out + line * L;
+        c.out = a.out + lo * a.os_o + li * a.os_i;
     c.lds = smem + ln * lds_padded_len(L);
     c.twd = a.tw;
     c.t = tid - ln * TPL;
@@ -272,6 +278,8 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
     LineFFT<T, L, TPL, decltype(c), typename RL<L, P>::type>::run(c);
 }
 
+// Lines are mapped as in ContigArgs; offsets count complex elements of the
+// complex side and pairs of reals (complex-sized units) of the real side.
 template <typename T> struct RealArgs {
     const void* in;
     void* out;
@@ -279,6 +287,8 @@ template <typename T> struct RealArgs {
     const cx<T>* tw2; // exp(-2 pi i k / n2)
     int nlines;
     int lines_per_wg;
+    int ni;
+    long long is_o, is_i, os_o, os_i;
 };
 
 // L = M = n2 / 2.
@@ -294,7 +304,8 @@ __global__ __launch_bounds__(1024) void k_r2c_z(RealArgs<T> a)
     const long long line = (long long)blockIdx.x * a.lines_per_wg + ln;
     R2CCtx<T, WL> c;
     c.valid = line < a.nlines;
-    c.in = reinterpret_cast<const V*>(a.in) + line * L;
+    const long long lo = line / a.ni, li = line - lo * a.ni;
+    c.in = reinterpret_cast<const V*>(a.in) + lo * a.is_o + li * a.is_i;
     c.lds = smem + ln * lds_padded_len(L + 1);
     c.twd = a.tw;
     c.t = tid - ln * TPL;
@@ -302,7 +313,7 @@ __global__ __launch_bounds__(1024) void k_r2c_z(RealArgs<T> a)
     c.sync();
     if (!c.valid) return;
     // X[k] = (a + b)/2 - (i/2) w^k (a - b),  a = Z[k mod M], b = conj(Z[(M - k) mod M])
-    V* out = reinterpret_cast<V*>(a.out) + line * (L + 1);
+    V* out = reinterpret_cast<V*>(a.out) + lo * a.os_o + li * a.os_i;
     const T half = T(0.5);
     for (int k = c.t; k <= L; k += TPL) {
         V za = c.lds[lds_pad(k == L ? 0 : k)];
@@ -325,14 +336,15 @@ __global__ __launch_bounds__(1024) void k_c2r_z(RealArgs<T> a)
     const long long line = (long long)blockIdx.x * a.lines_per_wg + ln;
     C2RCtx<T, WL> c;
     c.valid = line < a.nlines;
+    const long long lo = line / a.ni, li = line - lo * a.ni;
     c.lds = smem + ln * lds_padded_len(L + 1);
     c.twd = a.tw;
     c.twd2 = a.tw2;
     c.t = tid - ln * TPL;
     c.M = L;
-    c.out = reinterpret_cast<V*>(a.out) + line * L;
+    c.out = reinterpret_cast<V*>(a.out) + lo * a.os_o + li * a.os_i;
     if (c.valid) {
-        const V* in = reinterpret_cast<const V*>(a.in) + line * (L + 1);
+        const V* in = reinterpret_cast<const V*>(a.in) + lo * a.is_o + li * a.is_i;
         for (int k = c.t; k <= L; k += TPL) c.lds[lds_pad(k)] = in[k];
     }
     c.sync();

@@ -6,6 +6,7 @@
 // reads the caller's input; every later pass works in place on the output
 // (or, for C2R, on the workspace, so the input is preserved).
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -152,6 +153,7 @@ FastDiv make_fastdiv(uint32_t d)
 // ---------------------------------------------------------------- geometry
 
 static const size_t kLdsBudget = 64 * 1024;
+static const size_t kLdsMax = 160 * 1024;
 
 void set_contig_geometry(Pass& p, int prec, int tpl, int L, long long nlines, int lds_len)
 {
@@ -160,13 +162,23 @@ void set_contig_geometry(Pass& p, int prec, int tpl, int L, long long nlines, in
     if (lpw < 1) lpw = 1;
     while (lpw > 1 && (size_t)lpw * lds_len * esz > kLdsBudget) lpw /= 2;
     // keep enough workgroups to fill the chip when the batch is small
-    while (lpw > 1 && (nlines + lpw - 1) / lpw < 1024) lpw /= 2;
+    while (lpw > 1 && lpw * tpl > 64 && (nlines + lpw - 1) / lpw < 1024) lpw /= 2;
     p.L = L;
     p.nlines = nlines;
     p.lines_per_wg = lpw;
     p.grid = (unsigned)((nlines + lpw - 1) / lpw);
     p.block = (unsigned)(lpw * tpl);
     p.shmem = (size_t)lpw * lds_len * esz;
+    set_line_map(p, (int)(nlines > 0 ? nlines : 1), 0, L, 0, L);
+}
+
+void set_line_map(Pass& p, int ni, long long is_o, long long is_i, long long os_o, long long os_i)
+{
+    p.ni = ni;
+    p.is_o = is_o;
+    p.is_i = is_i;
+    p.os_o = os_o;
+    p.os_i = os_i;
 }
 
 static int ilog2(int v)
@@ -182,6 +194,10 @@ void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int group
     int B = 16;
     if (forceB > 0) {
         B = forceB;
+        while (B > 1 && ((size_t)B * tpl > 1024 || (size_t)B * L * esz > kLdsMax)) B /= 2;
+        while (B * tpl < 256 && B < 64 && (size_t)(2 * B) * L * esz <= kLdsBudget) B *= 2;
+        int cp = 1 << ilog2(cols < 1 ? 1 : cols);
+        if (cp < B) B = cp;
     } else {
         while (B * tpl < 256 && B < 64) B *= 2;
         while (B > 1 && ((size_t)B * tpl > 1024 || (size_t)B * L * esz > kLdsBudget)) B /= 2;
@@ -201,6 +217,21 @@ void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int group
 
 // ----------------------------------------------------------------- launch
 
+// Kernels whose dynamic LDS exceeds the default 64 KiB limit are opted in
+// once (gfx950 has 160 KiB of LDS per CU).
+static std::mutex g_lds_mu;
+static std::map<const void*, size_t> g_lds_set;
+
+static void ensure_lds(const void* fn, size_t bytes)
+{
+    if (bytes <= 65536) return;
+    std::lock_guard<std::mutex> g(g_lds_mu);
+    size_t& cur = g_lds_set[fn];
+    if (cur >= bytes) return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        cur = bytes;
+}
+
 template <typename T>
 static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStream_t s)
 {
@@ -218,7 +249,13 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.sgn = (T)p.sgn;
         a.pm = p.fd;
         a.pblk = p.blk;
+        a.ni = p.ni;
+        a.is_o = p.is_o;
+        a.is_i = p.is_i;
+        a.os_o = p.os_o;
+        a.os_i = p.os_i;
         auto fn = p.kind == P_CONTIG ? v.contig : v.contig_pack;
+        ensure_lds(reinterpret_cast<const void*>(fn), p.shmem);
         hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.block), p.shmem, s, a);
         break;
     }
@@ -240,6 +277,7 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.split = p.fd;
         a.s_hi = p.blk;
         auto fn = p.kind == P_STRIDED ? v.strided : v.strided_split;
+        ensure_lds(reinterpret_cast<const void*>(fn), p.shmem);
         hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.block), p.shmem, s, a);
         break;
     }
@@ -252,7 +290,13 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.tw2 = (const V*)p.tw2;
         a.nlines = (int)p.nlines;
         a.lines_per_wg = p.lines_per_wg;
+        a.ni = p.ni;
+        a.is_o = p.is_o;
+        a.is_i = p.is_i;
+        a.os_o = p.os_o;
+        a.os_i = p.os_i;
         auto fn = p.kind == P_R2C ? v.r2c : v.c2r;
+        ensure_lds(reinterpret_cast<const void*>(fn), p.shmem);
         hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.block), p.shmem, s, a);
         break;
     }
@@ -278,6 +322,10 @@ hipError_t launch_pass(const Pass& p, int prec, const void* src, void* dst, hipS
 
 int get_twiddles(Plan& plan, int L, void** out)
 {
+    if (plan.plan_only) {
+        *out = nullptr;
+        return MIFFT_OK;
+    }
     auto it = plan.twiddles.find(L);
     if (it != plan.twiddles.end()) {
         *out = it->second;
@@ -319,9 +367,36 @@ static int make_contig(Plan& plan, Pass& p, int L, long long nlines, int vidx)
     return MIFFT_OK;
 }
 
+// Column-tile shape of a strided pass: aim at 256-byte rows (B = 32 complex64
+// or 16 complex128), the widest row that keeps the tile within 128 KiB of LDS
+// and the workgroup within 1024 threads, trying the variants of L with the
+// most threads per line first.
+static void choose_strided(const Plan& plan, int L, int* vidx, int* B)
+{
+    const int esz = (int)plan.esz;
+    std::vector<int> cands;
+    for (int i = 0; i < variant_count(plan.prec); ++i)
+        if (variant_L(plan.prec, i) == L && variant_policy(plan.prec, i) == 0) cands.push_back(i);
+    std::sort(cands.begin(), cands.end(), [&](int a, int b) {
+        return variant_tpl(plan.prec, a) > variant_tpl(plan.prec, b);
+    });
+    for (int b = 256 / esz; b >= 1; b /= 2)
+        for (int v : cands) {
+            const int tpl = variant_tpl(plan.prec, v);
+            if ((long long)tpl * b <= 1024 && (size_t)b * L * esz <= 128 * 1024) {
+                *vidx = v;
+                *B = b;
+                return;
+            }
+        }
+    *vidx = default_variant(plan.prec, L);
+    *B = 1;
+}
+
 static int make_strided(Plan& plan, Pass& p, int L, int cols, int groups, long long es,
                         long long gs, int vidx, int forceB)
 {
+    if (forceB == 0) choose_strided(plan, L, &vidx, &forceB);
     p.kind = P_STRIDED;
     p.vidx = vidx;
     int rc = get_twiddles(plan, L, (void**)&p.tw);
@@ -330,24 +405,6 @@ static int make_strided(Plan& plan, Pass& p, int L, int cols, int groups, long l
     p.es_in = p.es_out = es;
     p.gs_in = p.gs_out = gs;
     return MIFFT_OK;
-}
-
-// Pass over axis `axis` (0 = x, 1 = y, 2 = z) of a complex [n0][n1][nc] array.
-static int make_axis_pass(Plan& plan, Pass& p, int axis, int nc, int sgn)
-{
-    const int n[3] = {plan.n0, plan.n1, nc};
-    const int L = n[axis];
-    const int vidx = default_variant(plan.prec, L);
-    if (vidx < 0) return set_error(MIFFT_ERR_UNSUPPORTED, "no kernel for length %d", L);
-    int rc;
-    if (axis == 2)
-        rc = make_contig(plan, p, L, (long long)plan.n0 * plan.n1, vidx);
-    else if (axis == 1)
-        rc = make_strided(plan, p, L, nc, plan.n0, nc, (long long)plan.n1 * nc, vidx, 0);
-    else
-        rc = make_strided(plan, p, L, plan.n1 * nc, 1, (long long)plan.n1 * nc, 0, vidx, 0);
-    p.sgn = sgn;
-    return rc;
 }
 
 static int make_real_z(Plan& plan, Pass& p, PassKind kind)
@@ -363,112 +420,237 @@ static int make_real_z(Plan& plan, Pass& p, PassKind kind)
     if (rc) return rc;
     set_contig_geometry(p, plan.prec, variant_tpl(plan.prec, vidx), M,
                         (long long)plan.n0 * plan.n1, lds_padded_len(M + 1));
+    // complex side: lines of M + 1; real side: lines of M pairs
+    const long long cl = M + 1, rl = M;
+    if (kind == P_R2C)
+        set_line_map(p, (int)p.nlines, 0, rl, 0, cl);
+    else
+        set_line_map(p, (int)p.nlines, 0, cl, 0, rl);
     return MIFFT_OK;
+}
+
+static int need_variant(Plan& plan, int L, int* v)
+{
+    *v = default_variant(plan.prec, L);
+    if (*v < 0) return set_error(MIFFT_ERR_UNSUPPORTED, "no kernel for length %d", L);
+    return MIFFT_OK;
+}
+
+// When the x-lines of the standard layout are far apart (stride n1 * n2c), a
+// strided read of them is slow: every row of a column tile sits in a
+// different translation page.  Strided writes with the same stride are
+// cheap.  So the y-pass writes its output transposed, W[k1][x][k2] (stride
+// n0 n2c between k1), and the x-pass then reads W with stride n2c and writes
+// the standard layout; the inverse mirrors this.  This costs a workspace of
+// the full (half) array.
+static bool want_transposed(const Plan& plan, int nc)
+{
+    if (plan.n0 < 2 || plan.n1 < 2) return false;
+    const size_t xstride = (size_t)plan.n1 * nc * plan.esz;
+    return xstride >= (size_t)256 * 1024;
 }
 
 int build_plan(Plan& plan, unsigned /*flags*/)
 {
     const bool real = plan.kind == MIFFT_R2C;
-    const int nc = real ? plan.n2 / 2 + 1 : plan.n2;
-    const size_t half_bytes = (size_t)plan.n0 * plan.n1 * nc * plan.esz;
-    int rc;
-    // ---- forward: z, y, x
+    const int n0 = plan.n0, n1 = plan.n1, n2 = plan.n2;
+    const int nc = real ? n2 / 2 + 1 : n2;
+    const long long plane = (long long)n1 * nc; // x stride of the standard layout
+    const size_t half_bytes = (size_t)n0 * n1 * nc * plan.esz;
+    const bool T = want_transposed(plan, nc);
+    plan.transposed = T;
+    const bool has_z = real || n2 > 1;
+    int rc, vy = -1, vx = -1, vz = -1;
+    if (n1 > 1 && (rc = need_variant(plan, n1, &vy))) return rc;
+    if (n0 > 1 && (rc = need_variant(plan, n0, &vx))) return rc;
+    if (!real && n2 > 1 && (rc = need_variant(plan, n2, &vz))) return rc;
+
+    // ---------------- forward: z, y, x (Algorithm 1, left column)
+    plan.fwd.clear();
     if (real) {
         Pass z;
         if ((rc = make_real_z(plan, z, P_R2C))) return rc;
-        z.src = B_IN;
-        z.dst = B_OUT;
         plan.fwd.push_back(z);
-    } else if (plan.n2 > 1) {
+    } else if (has_z) {
         Pass z;
-        if ((rc = make_axis_pass(plan, z, 2, nc, +1))) return rc;
+        if ((rc = make_contig(plan, z, n2, (long long)n0 * n1, vz))) return rc;
+        z.sgn = +1;
         plan.fwd.push_back(z);
     }
-    if (plan.n1 > 1) {
+    if (n1 > 1) {
         Pass y;
-        if ((rc = make_axis_pass(plan, y, 1, nc, +1))) return rc;
+        // tile = (x, B columns of k2); lines along y with stride nc
+        if ((rc = make_strided(plan, y, n1, nc, n0, nc, plane, vy, 0))) return rc;
+        if (T) {
+            y.es_out = (long long)n0 * nc; // W[k1][x][k2]
+            y.gs_out = nc;
+        }
+        y.sgn = +1;
         plan.fwd.push_back(y);
     }
-    if (plan.n0 > 1) {
+    if (n0 > 1) {
         Pass x;
-        if ((rc = make_axis_pass(plan, x, 0, nc, +1))) return rc;
+        if (T) {
+            // tile = (k1, B columns of k2) of W; lines along x with stride nc
+            if ((rc = make_strided(plan, x, n0, nc, n1, nc, (long long)n0 * nc, vx, 0))) return rc;
+            x.es_out = plane; // standard layout X[k0][k1][k2]
+            x.gs_out = nc;
+        } else {
+            if ((rc = make_strided(plan, x, n0, (int)plane, 1, plane, 0, vx, 0))) return rc;
+        }
+        x.sgn = +1;
         plan.fwd.push_back(x);
     }
-    // ---- inverse: x, y, z
-    if (plan.n0 > 1) {
-        Pass x;
-        if ((rc = make_axis_pass(plan, x, 0, nc, -1))) return rc;
-        plan.inv.push_back(x);
+    if (plan.fwd.empty()) { // 1 x 1 x 1 C2C: the identity
+        Pass c;
+        c.kind = P_COPY;
+        c.bytes = plan.esz;
+        plan.fwd.push_back(c);
     }
-    if (plan.n1 > 1) {
+    // buffers
+    {
+        auto& f = plan.fwd;
+        for (size_t i = 0; i < f.size(); ++i) {
+            f[i].src = i == 0 ? B_IN : B_OUT;
+            f[i].dst = B_OUT;
+        }
+        if (T) {
+            // ..., y: OUT (or IN) -> WS, x: WS -> OUT
+            Pass& y = f[f.size() - 2];
+            Pass& x = f[f.size() - 1];
+            y.dst = B_WS;
+            x.src = B_WS;
+            x.dst = B_OUT;
+        }
+    }
+
+    // ---------------- inverse
+    // Standard layout: x^-1, y^-1, z^-1 (Algorithm 1, right column), in
+    // place after the first pass (C2R keeps its input: workspace).
+    // Transposed: y^-1 (input -> W, transposing), x^-1 in place on W, then
+    // z^-1 reading the lines of W in transposed order.  The x and y inverses
+    // act on different axes of the same array and commute exactly in exact
+    // arithmetic, so the order only changes rounding.
+    plan.inv.clear();
+    if (T) {
         Pass y;
-        if ((rc = make_axis_pass(plan, y, 1, nc, -1))) return rc;
+        if ((rc = make_strided(plan, y, n1, nc, n0, nc, plane, vy, 0))) return rc;
+        y.es_out = (long long)n0 * nc;
+        y.gs_out = nc;
+        y.sgn = -1;
+        y.src = B_IN;
+        y.dst = B_WS;
         plan.inv.push_back(y);
-    }
-    if (real) {
-        Pass z;
-        if ((rc = make_real_z(plan, z, P_C2R))) return rc;
-        plan.inv.push_back(z);
-    } else if (plan.n2 > 1) {
-        Pass z;
-        if ((rc = make_axis_pass(plan, z, 2, nc, -1))) return rc;
-        plan.inv.push_back(z);
-    }
-    // ---- buffers: the first pass reads the input, the others run in place
-    if (!real) {
-        for (auto* list : {&plan.fwd, &plan.inv}) {
-            for (size_t i = 0; i < list->size(); ++i) {
-                (*list)[i].src = i == 0 ? B_IN : B_OUT;
-                (*list)[i].dst = B_OUT;
+        Pass x;
+        if ((rc = make_strided(plan, x, n0, nc, n1, nc, (long long)n0 * nc, vx, 0))) return rc;
+        x.sgn = -1;
+        x.src = x.dst = B_WS;
+        if (!has_z) { // no z-pass to undo the transposition: x^-1 writes the standard layout
+            x.es_out = plane;
+            x.gs_out = nc;
+            x.dst = B_OUT;
+        }
+        plan.inv.push_back(x);
+        if (has_z) {
+            Pass z;
+            if (real) {
+                if ((rc = make_real_z(plan, z, P_C2R))) return rc;
+                // line (x, y) of the output is line (y, x) of W
+                set_line_map(z, n1, (long long)nc, (long long)n0 * nc, (long long)n1 * (n2 / 2),
+                             (long long)(n2 / 2));
+            } else {
+                if ((rc = make_contig(plan, z, n2, (long long)n0 * n1, vz))) return rc;
+                set_line_map(z, n1, (long long)n2, (long long)n0 * n2, (long long)n1 * n2, (long long)n2);
+                z.sgn = -1;
             }
-            if (list->empty()) { // 1 x 1 x 1: the transform is the identity
-                Pass c;
-                c.kind = P_COPY;
-                c.bytes = plan.esz;
-                c.src = B_IN;
-                c.dst = B_OUT;
-                list->push_back(c);
-            }
+            z.src = B_WS;
+            z.dst = B_OUT;
+            plan.inv.push_back(z);
         }
     } else {
-        for (size_t i = 1; i < plan.fwd.size(); ++i) plan.fwd[i].src = plan.fwd[i].dst = B_OUT;
-        // C2R: complex passes go input -> workspace -> workspace, the last
-        // (z) pass reads the workspace (or the input if it is the only pass).
-        for (size_t i = 0; i + 1 < plan.inv.size(); ++i) {
-            plan.inv[i].src = i == 0 ? B_IN : B_WS;
-            plan.inv[i].dst = B_WS;
+        if (n0 > 1) {
+            Pass x;
+            if ((rc = make_strided(plan, x, n0, (int)plane, 1, plane, 0, vx, 0))) return rc;
+            x.sgn = -1;
+            plan.inv.push_back(x);
         }
-        plan.inv.back().src = plan.inv.size() == 1 ? B_IN : B_WS;
-        plan.inv.back().dst = B_OUT;
-        plan.ws_bytes = plan.inv.size() > 1 ? half_bytes : 0;
-        // Poisson: R2C into the workspace, y, x, multiply, x^-1, y^-1, C2R out.
-        plan.poisson.clear();
-        Pass z = plan.fwd[0];
-        z.src = B_IN;
-        z.dst = B_WS;
-        plan.poisson.push_back(z);
-        for (size_t i = 1; i < plan.fwd.size(); ++i) {
-            Pass q = plan.fwd[i];
-            q.src = q.dst = B_WS;
+        if (n1 > 1) {
+            Pass y;
+            if ((rc = make_strided(plan, y, n1, nc, n0, nc, plane, vy, 0))) return rc;
+            y.sgn = -1;
+            plan.inv.push_back(y);
+        }
+        if (real) {
+            Pass z;
+            if ((rc = make_real_z(plan, z, P_C2R))) return rc;
+            plan.inv.push_back(z);
+        } else if (has_z) {
+            Pass z;
+            if ((rc = make_contig(plan, z, n2, (long long)n0 * n1, vz))) return rc;
+            z.sgn = -1;
+            plan.inv.push_back(z);
+        }
+        if (plan.inv.empty()) {
+            Pass c;
+            c.kind = P_COPY;
+            c.bytes = plan.esz;
+            plan.inv.push_back(c);
+        }
+        auto& v = plan.inv;
+        if (!real) {
+            for (size_t i = 0; i < v.size(); ++i) {
+                v[i].src = i == 0 ? B_IN : B_OUT;
+                v[i].dst = B_OUT;
+            }
+        } else {
+            // complex passes input -> workspace -> workspace; C2R reads the
+            // workspace (or the input when it is the only pass)
+            for (size_t i = 0; i + 1 < v.size(); ++i) {
+                v[i].src = i == 0 ? B_IN : B_WS;
+                v[i].dst = B_WS;
+            }
+            v.back().src = v.size() == 1 ? B_IN : B_WS;
+            v.back().dst = B_OUT;
+        }
+    }
+    bool inv_uses_ws = false, fwd_uses_ws = false;
+    for (const Pass& q : plan.inv) inv_uses_ws |= (q.src == B_WS || q.dst == B_WS);
+    for (const Pass& q : plan.fwd) fwd_uses_ws |= (q.src == B_WS || q.dst == B_WS);
+    plan.ws_bytes = (inv_uses_ws || fwd_uses_ws) ? half_bytes : 0;
+
+    // ---------------- Poisson (R2C plans): forward into A, multiply, inverse
+    // out of A.  Buffers: A = first half of the Poisson workspace, B = the
+    // second half (used when the plan runs transposed).
+    plan.poisson.clear();
+    plan.poisson_ws_bytes = 0;
+    if (real) {
+        auto remap = [](BufId b, BufId in, BufId out, BufId ws) {
+            return b == B_IN ? in : b == B_OUT ? out : b == B_WS ? ws : b;
+        };
+        // forward: IN -> A (its OUT), workspace B
+        for (Pass q : plan.fwd) {
+            q.src = remap(q.src, B_IN, B_SEND, B_RECV);
+            q.dst = remap(q.dst, B_IN, B_SEND, B_RECV);
             plan.poisson.push_back(q);
         }
         Pass m;
         m.kind = P_POISSON;
-        m.n0 = plan.n0;
-        m.n1 = plan.n1;
+        m.n0 = n0;
+        m.n1 = n1;
         m.n2c = nc;
-        m.scale = 1.0 / ((double)plan.n0 * plan.n1 * plan.n2);
-        m.src = m.dst = B_WS;
+        m.scale = 1.0 / ((double)n0 * n1 * n2);
+        m.src = m.dst = B_SEND;
         plan.poisson.push_back(m);
-        for (size_t i = 0; i < plan.inv.size(); ++i) {
-            Pass q = plan.inv[i];
-            q.src = B_WS;
-            q.dst = (i + 1 == plan.inv.size()) ? B_OUT : B_WS;
+        // inverse: A -> ... -> OUT, workspace B
+        for (Pass q : plan.inv) {
+            q.src = remap(q.src, B_SEND, B_OUT, B_RECV);
+            q.dst = remap(q.dst, B_SEND, B_OUT, B_RECV);
             plan.poisson.push_back(q);
         }
-        plan.poisson_ws_bytes = half_bytes;
-        if (plan.poisson_ws_bytes > plan.ws_bytes) plan.ws_bytes = plan.poisson_ws_bytes;
+        plan.poisson_ws_bytes = 2 * half_bytes;
+        if (plan.poisson_ws_bytes > plan.ws_bytes) plan.default_ws_bytes = plan.poisson_ws_bytes;
     }
+    if (plan.ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.ws_bytes;
     return MIFFT_OK;
 }
 

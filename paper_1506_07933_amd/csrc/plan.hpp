@@ -37,9 +37,11 @@ struct Pass {
     int vidx = -1; // index into the variant table of the plan's precision
     BufId src = B_NONE, dst = B_NONE;
     int sgn = 1;   // +1 forward, -1 inverse
-    // contiguous / real passes
+    // contiguous / real passes: line l at (l / ni) * s_o + (l % ni) * s_i
     long long nlines = 0;
     int lines_per_wg = 1;
+    int ni = 1;
+    long long is_o = 0, is_i = 0, os_o = 0, os_i = 0;
     // strided passes
     int B = 1, log2B = 0, cols = 0, tiles_per_group = 0, groups = 0;
     long long gs_in = 0, gs_out = 0, es_in = 0, es_out = 0;
@@ -65,6 +67,10 @@ struct TuneChoice {
 class Plan {
 public:
     int n0 = 1, n1 = 1, n2 = 1, kind = MIFFT_C2C, prec = MIFFT_FP32;
+    // The y-pass writes a transposed intermediate W[ky][x][k2] into the
+    // workspace so that the x-pass reads with a small stride (see plan.hip).
+    bool transposed = false;
+    bool plan_only = false; // no device resources: describe only
     bool pencil = false;
     int p0 = 1, p1 = 1;
     int device = 0;
@@ -74,7 +80,8 @@ public:
     Pass pz, pz_pack, pk, upk, py, py_split;
     std::map<int, void*> twiddles; // length -> device table
     void* ws = nullptr;
-    size_t ws_bytes = 0;
+    size_t ws_bytes = 0;         // workspace an execute call needs
+    size_t default_ws_bytes = 0; // size of the plan's own workspace (covers Poisson too)
     size_t poisson_ws_bytes = 0;
     // opt-in per-pass event timing
     std::vector<hipEvent_t> prof_events; // max_calls * (max passes + 1)
@@ -101,6 +108,7 @@ FastDiv make_fastdiv(uint32_t d);
 
 // Launch geometry heuristics.
 void set_contig_geometry(Pass& p, int prec, int tpl, int L, long long nlines, int lds_len);
+void set_line_map(Pass& p, int ni, long long is_o, long long is_i, long long os_o, long long os_i);
 void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int groups, int forceB);
 
 // Enqueue one pass with resolved buffers.

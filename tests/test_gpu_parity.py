@@ -213,7 +213,7 @@ def test_r2c_small_and_uneven(shape):
 # -------------------------------------------------------------- Poisson
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [64, 128])
+@pytest.mark.parametrize("n", [64, 128, 256])
 def test_poisson_solve(prec, n):
     from paper_1506_07933_amd import Plan
     f, (ks, amp, ph) = synth.poisson_rhs(n, seed=n, dtype=RDT[prec])

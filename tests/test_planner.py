@@ -1,0 +1,109 @@
+"""Planner checks on the CPU (MIFFT_PLAN_ONLY: pass lists and launch shapes,
+no device).  They pin the launch configurations the GPU tests and the
+benchmark rely on: the kernel grids cover every line / column exactly, LDS
+and workgroup sizes stay within the gfx950 limits, and the transposed
+intermediate is used where the x-stride is large."""
+import ctypes
+import re
+
+import pytest
+
+from paper_1506_07933_amd._lib import MIFFT_PLAN_ONLY, lib
+from paper_1506_07933_amd.fft import plan_describe, plan_destroy
+
+
+def plan_only(n0, n1, n2, kind=0, prec=0):
+    h = ctypes.c_void_p()
+    rc = lib.mifft_plan_create(ctypes.byref(h), n0, n1, n2, kind, prec, MIFFT_PLAN_ONLY)
+    assert rc == 0, lib.mifft_last_error()
+    text = plan_describe(h.value)
+    ws = lib.mifft_workspace_bytes(h.value)
+    pws = lib.mifft_poisson_ws_bytes(h.value)
+    plan_destroy(h.value)
+    passes = []
+    for line in text.splitlines():
+        d = dict(kv.split("=") for kv in line.split()[1:])
+        d["dir"] = line.split()[0]
+        passes.append(d)
+    return passes, ws, pws
+
+
+def ints(d, *keys):
+    return [int(d[k]) for k in keys]
+
+
+SHAPES = [(512, 512, 512), (256, 256, 1024), (32, 32, 32), (100, 120, 144), (125, 125, 125),
+          (1, 1, 1), (3, 1024, 2), (1024, 3, 2), (64, 1, 1), (48, 64, 96), (2, 2, 2)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_launch_shapes_cover_and_fit(shape, prec, kind):
+    if kind == 1 and shape[2] % 2:
+        pytest.skip("R2C needs an even n2")
+    passes, ws, _ = plan_only(*shape, kind=kind, prec=prec)
+    esz = 16 if prec else 8
+    for p in passes:
+        if p["kind"] == "copy":
+            continue
+        grid, block, lds = ints(p, "grid", "block", "lds")
+        assert 1 <= block <= 1024
+        assert lds <= 160 * 1024
+        if p["kind"] in ("contig", "r2c_z", "c2r_z"):
+            lines, lpw, tpl = ints(p, "lines", "lpw", "tpl")
+            assert block == lpw * tpl
+            assert grid * lpw >= lines > (grid - 1) * lpw
+        elif p["kind"] == "strided":
+            B, cols, groups, tpl, L = ints(p, "B", "cols", "groups", "tpl", "L")
+            assert B & (B - 1) == 0 and block == B * tpl
+            tiles = -(-cols // B)
+            assert grid == tiles * groups
+            assert lds == B * L * esz
+
+
+def test_512_cube_uses_transposed_intermediate():
+    passes, ws, _ = plan_only(512, 512, 512)
+    assert ws == 512 ** 3 * 8
+    fwd = [p for p in passes if p["dir"] == "forward"]
+    assert [p["kind"] for p in fwd] == ["contig", "strided", "strided"]
+    y, x = fwd[1], fwd[2]
+    # y reads with stride n2 and writes W[k1][x][k2] (stride n0 n2)
+    assert y["es"] == "512/262144" and y["gs"] == "262144/512"
+    # x reads W with stride n2 and writes the standard layout (stride n1 n2)
+    assert x["es"] == "512/262144" and x["gs"] == "262144/512"
+    assert x["B"] == "32" and x["tpl"] == "32"
+
+
+def test_small_grid_keeps_standard_layout():
+    passes, ws, _ = plan_only(32, 32, 32, prec=1)
+    assert ws == 0
+    for p in passes:
+        if p["kind"] == "strided":
+            a, b = p["es"].split("/")
+            assert a == b
+
+
+def test_r2c_workspace_sizes():
+    _, ws, pws = plan_only(256, 256, 256, kind=1, prec=1)
+    half = 256 * 256 * 129 * 16
+    assert ws == half and pws == 2 * half
+
+
+def test_plan_only_cannot_execute():
+    h = ctypes.c_void_p()
+    assert lib.mifft_plan_create(ctypes.byref(h), 8, 8, 8, 0, 0, MIFFT_PLAN_ONLY) == 0
+    buf = ctypes.c_void_p(0x10000)
+    assert lib.mifft_execute_forward(h, buf, buf, None) == 5
+    assert lib.mifft_plan_destroy(h) == 0
+    assert lib.mifft_plan_create(ctypes.byref(h), 8, 8, 8, 0, 0, MIFFT_PLAN_ONLY | 1) == 1
+
+
+def test_pencil_plan_only_describes_fused_stages():
+    h = ctypes.c_void_p()
+    assert lib.mifft_plan_create_pencil(ctypes.byref(h), 1024, 1024, 1024, 4, 4, 0, 0,
+                                        MIFFT_PLAN_ONLY) == 0
+    text = plan_describe(h.value)
+    plan_destroy(h.value)
+    assert "pencil_z_pack kind=contig_pack L=1024" in text
+    assert "pencil_unpack_y kind=strided_unpack L=1024" in text
