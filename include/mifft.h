@@ -66,6 +66,8 @@ typedef enum {
                               uses, Sec. 3, Implementation Details); consults and
                               updates the wisdom file named by MIFFT_WISDOM */
 
+#define MIFFT_BATCH_KERNELS 4u /* batches: run the per-pass kernels of ordinary plans instead of
+                                  the persistent kernel (any supported length) */
 #define MIFFT_PLAN_ONLY 2u /* build the pass list without touching the device: the
                               plan can be described (mifft_plan_describe) and
                               destroyed, execute calls return MIFFT_ERR_BADPLAN */
@@ -181,13 +183,16 @@ size_t mifft_poisson_ws_bytes(mifft_plan plan);
 int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void* stream);
 
 /*
- * mifft_batch_create -- plan `count` independent 3-D C2C transforms of
- * uneven sizes (dims holds n0, n1, n2 per transform) that run as ONE
+ * mifft_batch_create -- plan `count` (1 .. 128) independent 3-D C2C transforms
+ * of uneven sizes (dims holds n0, n1, n2 per transform) that run as ONE
  * launch of a persistent kernel: workgroups pull (transform, pass, tile)
- * work items from a device queue in dependency order.  Per-length kernel
- * variants come from the same planner as single plans (MIFFT_TUNE times
- * them).  The execute call is graph-capturable; see mifft_batch_graph_launch.
- * Planning in the spirit of the FFTW / SPIRAL search the paper cites (Sec. 1).
+ * work items from a device queue in dependency order (all z-passes, then all
+ * y-passes, then all x-passes; a pass waits on a completion counter of the
+ * previous pass of its transform).  Every axis length must be 2 .. 256 with
+ * prime factors 2, 3, 5, unless MIFFT_BATCH_KERNELS asks for the per-pass
+ * kernels of ordinary plans instead (then MIFFT_TUNE tunes those plans).
+ * The batched local FFTs are the per-task work of Alg. 1 for many grids at
+ * once; scheduling them as one launch is this library's own design.
  */
 int mifft_batch_create(mifft_batch* out, int count, const int* dims, int kind, int prec,
                        unsigned flags);
@@ -205,6 +210,15 @@ int mifft_batch_graph_launch(mifft_batch batch, void* const* in, void* const* ou
                              void* stream);
 
 int mifft_batch_destroy(mifft_batch batch);
+
+/* Waits for the device and reports in *aborted whether any bounded wait of
+ * the persistent kernel ran out (1) since the last launch, in which case the
+ * outputs of that launch are not valid; 0 otherwise. */
+int mifft_batch_check(mifft_batch batch, int* aborted);
+
+/* Writes a one-line description of the batch (mode, passes, work items,
+ * persistent grid, LDS) into buf. */
+int mifft_batch_describe(mifft_batch batch, char* buf, size_t len);
 
 /*
  * Introspection for tests, benchmarks and the autotuner.

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmifft.so")
 
 MIFFT_C2C, MIFFT_R2C = 0, 1
 MIFFT_FP32, MIFFT_FP64 = 0, 1
-MIFFT_HEURISTIC, MIFFT_TUNE, MIFFT_PLAN_ONLY = 0, 1, 2
+MIFFT_HEURISTIC, MIFFT_TUNE, MIFFT_PLAN_ONLY, MIFFT_BATCH_KERNELS = 0, 1, 2, 4
 MIFFT_STAGE_Z, MIFFT_STAGE_PACK, MIFFT_STAGE_UNPACK, MIFFT_STAGE_Y = 1, 2, 4, 8
 STATUS = {0: "MIFFT_OK", 1: "MIFFT_ERR_INVALID", 2: "MIFFT_ERR_UNSUPPORTED",
           3: "MIFFT_ERR_NOMEM", 4: "MIFFT_ERR_DEVICE", 5: "MIFFT_ERR_BADPLAN"}
@@ -39,6 +39,8 @@ SIGNATURES = {
     "mifft_batch_execute_forward": (_i, [_vp, _vpp, _vpp, _vp]),
     "mifft_batch_graph_launch": (_i, [_vp, _vpp, _vpp, _vp]),
     "mifft_batch_destroy": (_i, [_vp]),
+    "mifft_batch_check": (_i, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    "mifft_batch_describe": (_i, [_vp, ctypes.c_char_p, _sz]),
     "mifft_plan_describe": (_i, [_vp, ctypes.c_char_p, _sz]),
     "mifft_profile_begin": (_i, [_vp, _i]),
     "mifft_profile_end": (_i, [_vp, ctypes.POINTER(ctypes.c_float), _i,

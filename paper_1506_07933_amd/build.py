@@ -36,8 +36,11 @@ def _jobs():
             jobs.append((os.path.join(CSRC, "variants.hip"),
                          os.path.join(OBJDIR, "variants_%s_%d.o" % (prec, c)),
                          ["-DMIFFT_REAL=%s" % prec, "-DMIFFT_CHUNK=%d" % c]))
+    for prec in ("float", "double"):
+        jobs.append((os.path.join(CSRC, "batch_kern.hip"),
+                     os.path.join(OBJDIR, "batch_kern_%s.o" % prec), ["-DMIFFT_REAL=%s" % prec]))
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith(".hip") and name != "variants.hip":
+        if name.endswith(".hip") and name not in ("variants.hip", "batch_kern.hip"):
             jobs.append((os.path.join(CSRC, name),
                          os.path.join(OBJDIR, name[:-4] + ".o"), []))
     return jobs

@@ -1,14 +1,382 @@
-// batch.hip -- batched uneven-size executor (placeholder).
+// batch.hip -- host side of the batched uneven-size executor.
+//
+// mifft_batch_create builds the queue of work items of a batch of 3-D C2C
+// transforms (z-passes of every transform, then y-passes, then x-passes; see
+// batch_kernels.hpp), uploads the pass table, generates twiddles per distinct
+// length and sizes the persistent grid.  Execution is one reset kernel and
+// one persistent kernel; mifft_batch_graph_launch captures the two into a
+// HIP graph once per set of buffers and replays it.  With MIFFT_BATCH_KERNELS
+// the batch runs instead as the per-pass kernels of ordinary plans (one plan
+// per distinct shape), which also covers lengths outside the persistent
+// kernel's menu.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <vector>
+
+#include "aux_kernels.hpp"
+#include "batch_kernels.hpp"
 #include "plan.hpp"
 
+extern "C" {
+hipError_t mifft_batch_launch_float(const void*, unsigned, size_t, int*, int, hipStream_t);
+hipError_t mifft_batch_launch_double(const void*, unsigned, size_t, int*, int, hipStream_t);
+int mifft_batch_blocks_per_cu_float(size_t);
+int mifft_batch_blocks_per_cu_double(size_t);
+int mifft_plan_create(mifft_plan*, int, int, int, int, int, unsigned);
+int mifft_execute_forward(mifft_plan, const void*, void*, void*);
+int mifft_plan_destroy(mifft_plan);
+}
+
+struct mifft_batch_s {
+    int count = 0, prec = MIFFT_FP32;
+    bool kernels = false; // per-pass kernel launches instead of the persistent kernel
+    std::vector<int> dims;
+    // persistent path
+    std::vector<mifft::BatchPass> passes;
+    mifft::BatchPass* d_passes = nullptr;
+    int* d_counters = nullptr;
+    int ncounters = 0;
+    int total_items = 0;
+    unsigned grid = 0;
+    size_t lds = 0;
+    std::map<int, void*> tw;
+    // per-pass kernel path: one plan per distinct shape
+    std::map<std::vector<int>, mifft_plan> plans;
+    // graph replay
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> g_in;
+    std::vector<void*> g_out;
+    ~mifft_batch_s();
+};
+
 namespace mifft {
-int batch_create(mifft_batch*, int, const int*, int, int, unsigned)
+
+static std::mutex g_bmu;
+static std::set<const void*> g_blive;
+
+static bool batch_live(const void* b)
 {
-    return set_error(MIFFT_ERR_UNSUPPORTED, "batched execution is not built yet");
+    std::lock_guard<std::mutex> g(g_bmu);
+    return g_blive.count(b) != 0;
 }
-int batch_execute(mifft_batch, void* const*, void* const*, void*, bool)
+
+static const int kMenu[] = {
+#define MIFFT_BATCH_LEN(I, LEN) LEN,
+    MIFFT_BATCH_MENU(MIFFT_BATCH_LEN)
+#undef MIFFT_BATCH_LEN
+};
+static const int kMenuN = (int)(sizeof(kMenu) / sizeof(kMenu[0]));
+
+static int menu_code(int L)
 {
-    return set_error(MIFFT_ERR_BADPLAN, "batched execution is not built yet");
+    for (int i = 0; i < kMenuN; ++i)
+        if (kMenu[i] == L) return i;
+    return -1;
 }
-int batch_destroy(mifft_batch b) { return b ? set_error(MIFFT_ERR_BADPLAN, "not a batch") : MIFFT_OK; }
+
+} // namespace mifft
+
+mifft_batch_s::~mifft_batch_s()
+{
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (cap_stream) hipStreamDestroy(cap_stream);
+    if (d_passes) hipFree(d_passes);
+    if (d_counters) hipFree(d_counters);
+    for (auto& kv : tw) hipFree(kv.second);
+    for (auto& kv : plans) mifft_plan_destroy(kv.second);
+}
+
+namespace mifft {
+
+int batch_create(mifft_batch* out, int count, const int* dims, int kind, int prec, unsigned flags)
+{
+    if (!out || !dims) return set_error(MIFFT_ERR_INVALID, "out / dims is NULL");
+    if (count < 1) return set_error(MIFFT_ERR_INVALID, "count must be >= 1");
+    if (kind != MIFFT_C2C && kind != MIFFT_R2C) return set_error(MIFFT_ERR_INVALID, "bad kind %d", kind);
+    if (prec != MIFFT_FP32 && prec != MIFFT_FP64) return set_error(MIFFT_ERR_INVALID, "bad precision %d", prec);
+    if (flags & ~(unsigned)(MIFFT_TUNE | MIFFT_BATCH_KERNELS))
+        return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if (kind != MIFFT_C2C) return set_error(MIFFT_ERR_UNSUPPORTED, "batches are C2C only");
+    if (count > kBatchMax) return set_error(MIFFT_ERR_UNSUPPORTED, "at most %d transforms per batch", kBatchMax);
+    const bool kernels = flags & MIFFT_BATCH_KERNELS;
+    for (int t = 0; t < count; ++t)
+        for (int a = 0; a < 3; ++a) {
+            const int L = dims[3 * t + a];
+            if (L < 1) return set_error(MIFFT_ERR_INVALID, "transform %d: extent %d < 1", t, L);
+            if (!supported_length(L))
+                return set_error(MIFFT_ERR_UNSUPPORTED, "transform %d: length %d unsupported", t, L);
+            if (!kernels && L > 1 && menu_code(L) < 0)
+                return set_error(MIFFT_ERR_UNSUPPORTED,
+                                 "transform %d: length %d has no persistent code path (2..256, factors "
+                                 "2, 3, 5); use MIFFT_BATCH_KERNELS",
+                                 t, L);
+        }
+    for (int t = 0; !kernels && t < count; ++t)
+        if (dims[3 * t] == 1 && dims[3 * t + 1] == 1 && dims[3 * t + 2] == 1)
+            return set_error(MIFFT_ERR_UNSUPPORTED,
+                             "transform %d is 1 x 1 x 1 (no pass to run); use MIFFT_BATCH_KERNELS", t);
+    int dev = 0;
+    int nd = 0;
+    if (hipGetDeviceCount(&nd) != hipSuccess || nd < 1)
+        return set_error(MIFFT_ERR_DEVICE, "no HIP device available");
+    hipGetDevice(&dev);
+
+    mifft_batch_s* b = new mifft_batch_s();
+    b->count = count;
+    b->prec = prec;
+    b->kernels = kernels;
+    b->dims.assign(dims, dims + 3 * count);
+    const size_t esz = prec == MIFFT_FP64 ? 16 : 8;
+
+    if (kernels) {
+        for (int t = 0; t < count; ++t) {
+            std::vector<int> key(dims + 3 * t, dims + 3 * t + 3);
+            if (b->plans.count(key)) continue;
+            mifft_plan p = nullptr;
+            int rc = mifft_plan_create(&p, key[0], key[1], key[2], MIFFT_C2C, prec, flags & MIFFT_TUNE);
+            if (rc) {
+                delete b;
+                return rc;
+            }
+            b->plans[key] = p;
+        }
+    } else {
+        // ---- passes in queue order: all z, then all y, then all x
+        std::vector<BatchPass>& P = b->passes;
+        std::vector<int> last(count, -1); // index of each transform's latest pass
+        size_t max_wave_lds = 0;
+        for (int stage = 0; stage < 3; ++stage) {
+            for (int t = 0; t < count; ++t) {
+                const int n0 = dims[3 * t], n1 = dims[3 * t + 1], n2 = dims[3 * t + 2];
+                const int L = stage == 0 ? n2 : (stage == 1 ? n1 : n0);
+                if (L == 1) continue;
+                BatchPass p{};
+                p.kind = stage == 0 ? 0 : 1;
+                p.code = menu_code(L);
+                p.L = L;
+                p.tpl = threads_per_line(L, 0, 1);
+                p.xform = t;
+                p.from_in = last[t] < 0 ? 1 : 0;
+                p.per_wave = 64 / p.tpl;
+                if (stage == 0) {
+                    p.units = (long long)n0 * n1;
+                    p.subtiles = (int)((p.units + p.per_wave - 1) / p.per_wave);
+                } else if (stage == 1) {
+                    p.cols = n2;
+                    p.gs = (long long)n1 * n2;
+                    p.es = n2;
+                    p.subtiles_per_group = (p.cols + p.per_wave - 1) / p.per_wave;
+                    p.subtiles = p.subtiles_per_group * n0;
+                    p.units = (long long)n0 * n2;
+                } else {
+                    p.cols = n1 * n2;
+                    p.gs = 0;
+                    p.es = (long long)n1 * n2;
+                    p.subtiles_per_group = (p.cols + p.per_wave - 1) / p.per_wave;
+                    p.subtiles = p.subtiles_per_group;
+                    p.units = p.cols;
+                }
+                // queue items of ~64 KiB of data, a multiple of the wavefronts per workgroup
+                const size_t sub_bytes = (size_t)p.per_wave * L * esz;
+                int spi = (int)((65536 + sub_bytes * kBatchWaves - 1) / (sub_bytes * kBatchWaves)) * kBatchWaves;
+                spi = std::max(kBatchWaves, std::min(spi, ((p.subtiles + kBatchWaves - 1) / kBatchWaves) * kBatchWaves));
+                p.sub_per_item = spi;
+                p.nitems = (p.subtiles + spi - 1) / spi;
+                p.dep = last[t];
+                p.dep_target = last[t] >= 0 ? P[last[t]].nitems : 0;
+                p.done = (int)P.size();
+                auto it = b->tw.find(L);
+                if (it == b->tw.end()) {
+                    void* w = nullptr;
+                    if (hipMalloc(&w, (size_t)L * esz) != hipSuccess) {
+                        delete b;
+                        return set_error(MIFFT_ERR_NOMEM, "twiddles");
+                    }
+                    hipError_t e = prec == MIFFT_FP64 ? launch_twiddles<double>((cx<double>*)w, L, nullptr)
+                                                      : launch_twiddles<float>((cx<float>*)w, L, nullptr);
+                    if (e != hipSuccess) {
+                        hipFree(w);
+                        delete b;
+                        return set_error(MIFFT_ERR_DEVICE, "twiddle kernel: %s", hipGetErrorString(e));
+                    }
+                    it = b->tw.emplace(L, w).first;
+                }
+                p.tw = it->second;
+                last[t] = (int)P.size();
+                P.push_back(p);
+                max_wave_lds = std::max(max_wave_lds, (size_t)batch_wave_lds(L, p.tpl));
+            }
+        }
+        int start = 0;
+        for (BatchPass& p : P) {
+            p.item_start = start;
+            start += p.nitems;
+        }
+        b->total_items = start;
+        b->ncounters = (int)P.size() + 2;
+        b->lds = max_wave_lds * esz * kBatchWaves;
+        if (hipMalloc(&b->d_passes, sizeof(BatchPass) * P.size()) != hipSuccess ||
+            hipMalloc(&b->d_counters, sizeof(int) * b->ncounters) != hipSuccess) {
+            delete b;
+            return set_error(MIFFT_ERR_NOMEM, "batch tables");
+        }
+        if (hipMemcpy(b->d_passes, P.data(), sizeof(BatchPass) * P.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(b->d_counters, 0, sizeof(int) * b->ncounters) != hipSuccess) {
+            delete b;
+            return set_error(MIFFT_ERR_DEVICE, "uploading the batch tables");
+        }
+        hipDeviceProp_t prop;
+        hipGetDeviceProperties(&prop, dev);
+        const int per_cu = prec == MIFFT_FP64 ? mifft_batch_blocks_per_cu_double(b->lds)
+                                              : mifft_batch_blocks_per_cu_float(b->lds);
+        long long grid = (long long)prop.multiProcessorCount * per_cu;
+        if (grid > b->total_items) grid = b->total_items;
+        b->grid = (unsigned)std::max(1LL, grid);
+    }
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete b;
+        return set_error(MIFFT_ERR_DEVICE, "batch set-up: %s", hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> g(g_bmu);
+        g_blive.insert(b);
+    }
+    *out = b;
+    return MIFFT_OK;
+}
+
+static int enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t s)
+{
+    if (b->kernels) {
+        for (int t = 0; t < b->count; ++t) {
+            std::vector<int> key(b->dims.begin() + 3 * t, b->dims.begin() + 3 * t + 3);
+            int rc = mifft_execute_forward(b->plans[key], in[t], out[t], s);
+            if (rc) return rc;
+        }
+        return MIFFT_OK;
+    }
+    hipError_t e;
+    if (b->prec == MIFFT_FP64) {
+        BatchArgs<double> a{};
+        a.passes = b->d_passes;
+        a.npass = (int)b->passes.size();
+        a.total_items = b->total_items;
+        a.counters = b->d_counters;
+        a.spin_limit = 1u << 22;
+        for (int t = 0; t < b->count; ++t) {
+            a.in[t] = (const cx<double>*)in[t];
+            a.out[t] = (cx<double>*)out[t];
+        }
+        e = mifft_batch_launch_double(&a, b->grid, b->lds, b->d_counters, b->ncounters, s);
+    } else {
+        BatchArgs<float> a{};
+        a.passes = b->d_passes;
+        a.npass = (int)b->passes.size();
+        a.total_items = b->total_items;
+        a.counters = b->d_counters;
+        a.spin_limit = 1u << 22;
+        for (int t = 0; t < b->count; ++t) {
+            a.in[t] = (const cx<float>*)in[t];
+            a.out[t] = (cx<float>*)out[t];
+        }
+        e = mifft_batch_launch_float(&a, b->grid, b->lds, b->d_counters, b->ncounters, s);
+    }
+    if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "batch launch: %s", hipGetErrorString(e));
+    return MIFFT_OK;
+}
+
+int batch_execute(mifft_batch b, void* const* in, void* const* out, void* stream, bool graph)
+{
+    if (!b) return set_error(MIFFT_ERR_INVALID, "batch is NULL");
+    if (!batch_live(b)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live batch");
+    if (!in || !out) return set_error(MIFFT_ERR_INVALID, "in / out arrays are NULL");
+    for (int t = 0; t < b->count; ++t) {
+        if (!in[t] || !out[t]) return set_error(MIFFT_ERR_INVALID, "transform %d: NULL buffer", t);
+        if (((uintptr_t)in[t] | (uintptr_t)out[t]) & 15u)
+            return set_error(MIFFT_ERR_INVALID, "transform %d: buffers must be 16-byte aligned", t);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!graph) return enqueue(b, in, out, s);
+    const bool same = b->exec && std::equal(b->g_in.begin(), b->g_in.end(), in) &&
+                      std::equal(b->g_out.begin(), b->g_out.end(), out);
+    if (!same) {
+        if (b->exec) hipGraphExecDestroy(b->exec);
+        if (b->graph) hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return set_error(MIFFT_ERR_DEVICE, "capture stream");
+        hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "begin capture: %s", hipGetErrorString(e));
+        int rc = enqueue(b, in, out, b->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap_stream, &g);
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "end capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            return set_error(MIFFT_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        b->graph = g;
+        b->g_in.assign(in, in + b->count);
+        b->g_out.assign(out, out + b->count);
+    }
+    hipError_t e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "graph launch: %s", hipGetErrorString(e));
+    return MIFFT_OK;
+}
+
+int batch_destroy(mifft_batch b)
+{
+    if (!b) return MIFFT_OK;
+    {
+        std::lock_guard<std::mutex> g(g_bmu);
+        if (!g_blive.erase(b)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live batch");
+    }
+    delete b;
+    return MIFFT_OK;
+}
+
+int batch_check(mifft_batch b, int* aborted)
+{
+    if (!b || !aborted) return set_error(MIFFT_ERR_INVALID, "NULL argument");
+    if (!batch_live(b)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live batch");
+    *aborted = 0;
+    if (b->kernels) return MIFFT_OK;
+    int flag = 0;
+    hipError_t e = hipMemcpy(&flag, b->d_counters + b->ncounters - 1, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "reading the abort flag: %s", hipGetErrorString(e));
+    *aborted = flag;
+    return MIFFT_OK;
+}
+
+int batch_describe(mifft_batch b, char* buf, size_t len)
+{
+    if (!b || !buf || !len) return set_error(MIFFT_ERR_INVALID, "NULL argument");
+    if (!batch_live(b)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live batch");
+    std::string s;
+    char line[256];
+    if (b->kernels) {
+        snprintf(line, sizeof(line), "mode=kernels transforms=%d shapes=%zu\n", b->count, b->plans.size());
+        s += line;
+    } else {
+        snprintf(line, sizeof(line), "mode=persistent transforms=%d passes=%zu items=%d grid=%u block=%d lds=%zu\n",
+                 b->count, b->passes.size(), b->total_items, b->grid, kBatchBlock, b->lds);
+        s += line;
+    }
+    snprintf(buf, len, "%s", s.c_str());
+    return MIFFT_OK;
+}
+
 } // namespace mifft

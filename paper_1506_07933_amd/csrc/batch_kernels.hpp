@@ -1,0 +1,362 @@
+// batch_kernels.hpp -- one persistent launch for many 3-D transforms of
+// uneven sizes.
+//
+// Every (transform, pass) of the batch is a run of work items; the items of
+// all z-passes come first in the queue, then all y-passes, then all
+// x-passes.  Persistent workgroups take items from a device counter in
+// queue order.  An item of a y- or x-pass first waits until every item of
+// the same transform's previous pass has completed (a per-pass completion
+// counter).  Because an item only ever waits for items that sit earlier in
+// the queue, and those were taken by workgroups that are already running
+// and never wait on anything later, the queue always drains, whether or not
+// all workgroups are resident.  Every wait is bounded as well: a wait that
+// exceeds its bound raises an abort flag that makes every workgroup leave.
+//
+// Inside an item each wavefront transforms its own lines (z) or its own
+// columns (y, x) with the Stockham engine, synchronising only within the
+// wavefront; lanes left over when the threads per line do not divide 64 work
+// on a private dummy line or column whose results are discarded.
+#pragma once
+
+#include <stddef.h>
+
+#include "kernels.hpp"
+
+namespace mifft {
+
+constexpr int kBatchMax = 128;      // transforms per batch (pointer slots in the kernel args)
+constexpr int kBatchBlock = 256;    // threads per workgroup (4 wavefronts)
+constexpr int kBatchWaves = kBatchBlock / 64;
+
+// Line lengths with a code path in the persistent kernel: every length up to
+// 256 with prime factors 2, 3, 5 whose threads per line fit one wavefront.
+#define MIFFT_BATCH_MENU(X)                                                                       \
+    X(0, 2) X(1, 3) X(2, 4) X(3, 5) X(4, 6) X(5, 8) X(6, 9) X(7, 10) X(8, 12) X(9, 15) X(10, 16)  \
+    X(11, 18) X(12, 20) X(13, 24) X(14, 25) X(15, 27) X(16, 30) X(17, 32) X(18, 36) X(19, 40)      \
+    X(20, 45) X(21, 48) X(22, 50) X(23, 54) X(24, 60) X(25, 64) X(26, 72) X(27, 75) X(28, 80)      \
+    X(29, 81) X(30, 90) X(31, 96) X(32, 100) X(33, 108) X(34, 120) X(35, 125) X(36, 128)           \
+    X(37, 135) X(38, 144) X(39, 150) X(40, 160) X(41, 162) X(42, 180) X(43, 192) X(44, 200)        \
+    X(45, 216) X(46, 225) X(47, 240) X(48, 250) X(49, 256)
+
+struct BatchPass {
+    int kind;     // 0: contiguous z-lines, 1: strided columns
+    int code;     // menu index of the line length
+    int L;
+    int tpl;      // threads per line
+    int xform;    // transform index (pointer slot)
+    int from_in;  // 1: read the transform's input, 0: work in place on its output
+    long long units;     // lines (kind 0) or columns over all groups (kind 1)
+    int per_wave;        // lines / columns per wavefront sub-tile
+    int subtiles;        // wavefront sub-tiles of this pass
+    int subtiles_per_group; // kind 1
+    int sub_per_item;    // sub-tiles per queue item (a multiple of the waves per workgroup)
+    int nitems;
+    int item_start;      // first queue index of this pass
+    int cols;            // kind 1: columns per group
+    long long gs, es;    // kind 1: group and element strides
+    int dep;             // completion counter to wait for, -1: none
+    int dep_target;      // items it must reach
+    int done;            // completion counter of this pass
+    const void* tw;      // twiddles of length L
+};
+
+template <typename T> struct BatchArgs {
+    const BatchPass* passes;
+    int npass;
+    int total_items;
+    int* counters;       // [0] queue head, [1 + p] completion of pass p, [1 + npass] abort flag
+    unsigned spin_limit; // bound on the polls of one wait
+    const cx<T>* in[kBatchMax];
+    cx<T>* out[kBatchMax];
+};
+
+// Dynamic LDS of the persistent kernel, named at file scope so that device
+// functions address it as LDS (not through generic pointers).
+extern __shared__ unsigned char mifft_batch_lds[];
+
+// Pointers read from memory are generic; the wave contexts hold them as
+// global (address space 1) pointers so the compiler emits global, not flat,
+// accesses, and the pass table is read through the constant address space
+// (scalar loads).
+#define MIFFT_GLOBAL __attribute__((address_space(1)))
+#define MIFFT_CONST __attribute__((address_space(4)))
+
+// Wave-local contexts -----------------------------------------------------
+
+// Native two-element vectors are copied across address spaces freely (HIP's
+// float2 / double2 classes are not), so global data moves as these.
+template <typename T> struct vec2_of;
+template <> struct vec2_of<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct vec2_of<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+template <typename T> struct WaveContigCtx {
+    using V = cx<T>;
+    typedef typename vec2_of<T>::type N2;
+    typedef MIFFT_GLOBAL N2 GN2;
+    static constexpr bool kSyncAfterFirstRead = false;
+    const GN2* in;
+    GN2* out;
+    V* lds;
+    const GN2* twd;
+    int t;
+    bool valid;
+    __device__ __forceinline__ V gload(int idx) const
+    {
+        N2 r = valid ? in[idx] : N2{T(0), T(0)};
+        return V{r.x, r.y};
+    }
+    __device__ __forceinline__ V lds_get(int idx) const { return lds[lds_pad(idx)]; }
+    __device__ __forceinline__ void lds_put(int idx, V v) { lds[lds_pad(idx)] = v; }
+    __device__ __forceinline__ void final_put(int idx, V v)
+    {
+        if (valid) out[idx] = N2{v.x, v.y};
+    }
+    __device__ __forceinline__ V tw(int e) const
+    {
+        N2 r = twd[e];
+        return V{r.x, r.y};
+    }
+    __device__ __forceinline__ void sync() const { wave_sync(); }
+};
+
+template <typename T> struct WaveStridedCtx {
+    using V = cx<T>;
+    typedef typename vec2_of<T>::type N2;
+    typedef MIFFT_GLOBAL N2 GN2;
+    static constexpr bool kSyncAfterFirstRead = false;
+    const GN2* in;
+    GN2* out;
+    V* lds; // column ci of the sub-tile: element idx at lds[idx * rs]
+    const GN2* twd;
+    int t;
+    int rs;
+    bool valid;
+    long long es;
+    __device__ __forceinline__ V gload(int idx) const
+    {
+        N2 r = valid ? in[(long long)idx * es] : N2{T(0), T(0)};
+        return V{r.x, r.y};
+    }
+    __device__ __forceinline__ V lds_get(int idx) const { return lds[idx * rs]; }
+    __device__ __forceinline__ void lds_put(int idx, V v) { lds[idx * rs] = v; }
+    __device__ __forceinline__ void final_put(int idx, V v)
+    {
+        if (valid) out[(long long)idx * es] = N2{v.x, v.y};
+    }
+    __device__ __forceinline__ V tw(int e) const
+    {
+        N2 r = twd[e];
+        return V{r.x, r.y};
+    }
+    __device__ __forceinline__ void sync() const { wave_sync(); }
+};
+
+// LDS (elements) one wavefront needs for a sub-tile of length L.
+__host__ __device__ constexpr int batch_wave_lds(int L, int tpl)
+{
+    const int per = 64 / tpl;
+    const int a = (per + 1) * lds_padded_len(L); // contiguous lines + a dummy line
+    const int b = L * (per + 1);                 // columns + a dummy column
+    return a > b ? a : b;
+}
+
+// Scalar copy of the fields a sub-tile needs (every field is uniform).
+struct PassU {
+    int kind, per_wave, subtiles_per_group, cols;
+    long long units, gs, es;
+    const void* tw;
+};
+
+__device__ __forceinline__ long long rfl64(long long v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ PassU load_pass(const MIFFT_CONST BatchPass* p)
+{
+    PassU u;
+    u.kind = __builtin_amdgcn_readfirstlane(p->kind);
+    u.per_wave = __builtin_amdgcn_readfirstlane(p->per_wave);
+    u.subtiles_per_group = __builtin_amdgcn_readfirstlane(p->subtiles_per_group);
+    u.cols = __builtin_amdgcn_readfirstlane(p->cols);
+    u.units = rfl64(p->units);
+    u.gs = rfl64(p->gs);
+    u.es = rfl64(p->es);
+    u.tw = (const void*)rfl64((long long)p->tw);
+    return u;
+}
+
+template <typename T, int L>
+__device__ __forceinline__ void batch_subtile(const PassU& p, const cx<T>* src, cx<T>* dst, int sub,
+                                              int lane, cx<T>* wlds)
+{
+    using V = cx<T>;
+    typedef MIFFT_GLOBAL typename vec2_of<T>::type GV;
+    constexpr int TPL = threads_per_line(L, 0, 1);
+    constexpr int per = 64 / TPL;
+    const int ui = lane / TPL; // line / column of this lane within the sub-tile
+    const int t = lane - ui * TPL;
+    if (p.kind == 0) {
+        WaveContigCtx<T> c;
+        const long long line = (long long)sub * per + ui;
+        c.valid = ui < per && line < p.units;
+        c.in = (const GV*)(src + line * L);
+        c.out = (GV*)(dst + line * L);
+        c.lds = wlds + (ui < per ? ui : per) * lds_padded_len(L);
+        c.twd = (const GV*)p.tw;
+        c.t = t;
+        LineFFT<T, L, TPL, WaveContigCtx<T>, typename RL<L, 0>::type>::run(c);
+    } else {
+        WaveStridedCtx<T> c;
+        const int g = sub / p.subtiles_per_group;
+        const int c0 = (sub - g * p.subtiles_per_group) * per;
+        const int col = c0 + ui;
+        c.valid = ui < per && col < p.cols;
+        const long long base = (long long)g * p.gs + col;
+        c.in = (const GV*)(src + base);
+        c.out = (GV*)(dst + base);
+        c.rs = per + 1;
+        c.lds = wlds + (ui < per ? ui : per);
+        c.twd = (const GV*)p.tw;
+        c.t = t;
+        c.es = p.es;
+        LineFFT<T, L, TPL, WaveStridedCtx<T>, typename RL<L, 0>::type>::run(c);
+    }
+}
+
+// One code path per length, kept out of line so each gets its own register
+// allocation: the wavefront's sub-tiles first + wave, first + wave + 4, ...
+template <typename T, int L>
+__device__ __noinline__ void batch_item(const BatchPass* pp, const cx<T>* src_g, cx<T>* dst_g, int first,
+                                        int last, int wave, int lane, int lds_off)
+{
+    const PassU p = load_pass((const MIFFT_CONST BatchPass*)pp);
+    const cx<T>* src = src_g;
+    cx<T>* dst = dst_g;
+    cx<T>* wlds = reinterpret_cast<cx<T>*>(mifft_batch_lds) + lds_off;
+#pragma nounroll
+    for (int s = first + wave; s < last; s += kBatchWaves) batch_subtile<T, L>(p, src, dst, s, lane, wlds);
+}
+
+template <typename T>
+__device__ __forceinline__ void batch_dispatch(int code, const BatchPass* p, const cx<T>* src, cx<T>* dst,
+                                               int first, int last, int wave, int lane, int wlds)
+{
+    switch (code) {
+#define MIFFT_BATCH_CASE(I, LEN)                                                                  \
+    case I:                                                                                       \
+        batch_item<T, LEN>(p, src, dst, first, last, wave, lane, wlds);                          \
+        break;
+        MIFFT_BATCH_MENU(MIFFT_BATCH_CASE)
+#undef MIFFT_BATCH_CASE
+    default:
+        break;
+    }
+}
+
+// Take the next queue item (or the end of the queue once the abort flag is up).
+__device__ __forceinline__ int batch_dequeue(int* head, int* abort_flag, int total)
+{
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return total;
+    return __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loop structure: every region that only thread 0 executes (the dequeue, the
+// dependency wait, the release and completion count) sits between two
+// workgroup barriers, and the loop's back edge leaves from a barrier.  With a
+// thread-0 region at the end of one iteration and another at the start of
+// the next, the compiler may merge them across the back edge and let the
+// other lanes run the next iteration's barrier before thread 0 has
+// published the next item.
+template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchArgs<T> a)
+{
+    using V = cx<T>;
+    __shared__ int s_item, s_abort;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    int* head = a.counters;
+    int* abort_flag = a.counters + 1 + a.npass;
+    if (tid == 0) {
+        s_item = batch_dequeue(head, abort_flag, a.total_items);
+        s_abort = 0;
+    }
+    __syncthreads();
+    for (int iter = 0;; ++iter) {
+        // uniform across the workgroup: keep the pass lookup and the code
+        // switch scalar
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= a.total_items) break;
+        if (iter > a.total_items) { // can only happen if the queue logic is broken: leave
+            if (tid == 0) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        // pass of this item: the last pass whose first item is <= item
+        int lo = 0, hi = a.npass - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (__builtin_amdgcn_readfirstlane(a.passes[mid].item_start) <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchPass* pp = a.passes + lo;
+        const int dep = __builtin_amdgcn_readfirstlane(pp->dep);
+        const int dep_target = __builtin_amdgcn_readfirstlane(pp->dep_target);
+        const int code = __builtin_amdgcn_readfirstlane(pp->code);
+        const int from_in = __builtin_amdgcn_readfirstlane(pp->from_in);
+        const int xform = __builtin_amdgcn_readfirstlane(pp->xform);
+        const int item_start = __builtin_amdgcn_readfirstlane(pp->item_start);
+        const int spi = __builtin_amdgcn_readfirstlane(pp->sub_per_item);
+        const int subtiles = __builtin_amdgcn_readfirstlane(pp->subtiles);
+        const int wl = __builtin_amdgcn_readfirstlane(batch_wave_lds(pp->L, pp->tpl));
+        const int done = __builtin_amdgcn_readfirstlane(pp->done);
+        if (dep >= 0) {
+            if (tid == 0) {
+                unsigned polls = 0;
+                while (__hip_atomic_load(a.counters + 1 + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                       dep_target) {
+                    if (++polls > a.spin_limit ||
+                        __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        s_abort = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+            if (__builtin_amdgcn_readfirstlane(s_abort)) break;
+        }
+        // The pointer slots are read straight from the kernel-argument segment
+        // (a uniform, dynamically indexed load) so the argument block is never
+        // copied to private memory.
+        const char* ka = (const char*)__builtin_amdgcn_kernarg_segment_ptr();
+        V* const* outs = reinterpret_cast<V* const*>(ka + offsetof(BatchArgs<T>, out));
+        const V* const* ins = reinterpret_cast<const V* const*>(ka + offsetof(BatchArgs<T>, in));
+        const V* src = from_in ? ins[xform] : outs[xform];
+        V* dst = outs[xform];
+        const int wlds = wave * wl; // this wavefront's slice of the dynamic LDS (elements)
+        const int first = (item - item_start) * spi;
+        const int last = first + spi < subtiles ? first + spi : subtiles;
+        batch_dispatch<T>(code, pp, src, dst, first, last, wave, lane, wlds);
+        // every wavefront releases its own stores at agent scope (waits for
+        // them and writes the L2 back) before the completion is counted
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(a.counters + 1 + done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_item = batch_dequeue(head, abort_flag, a.total_items);
+        }
+        __syncthreads(); // the next item is published
+    }
+}
+
+// Zero the queue head, the completion counters and the abort flag (a kernel,
+// not a memset, so the reset can be captured in a graph).
+template <typename T> __global__ void k_batch_reset(int* counters, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counters[i] = 0;
+}
+
+} // namespace mifft

@@ -19,6 +19,8 @@ const char* last_error_cstr();
 int batch_create(mifft_batch* out, int count, const int* dims, int kind, int prec, unsigned flags);
 int batch_execute(mifft_batch b, void* const* in, void* const* out, void* stream, bool graph);
 int batch_destroy(mifft_batch b);
+int batch_check(mifft_batch b, int* aborted);
+int batch_describe(mifft_batch b, char* buf, size_t len);
 int tune_plan(Plan& plan);
 } // namespace mifft
 
@@ -461,6 +463,18 @@ int mifft_batch_destroy(mifft_batch batch)
 {
     clear_error();
     return batch_destroy(batch);
+}
+
+int mifft_batch_check(mifft_batch batch, int* aborted)
+{
+    clear_error();
+    return batch_check(batch, aborted);
+}
+
+int mifft_batch_describe(mifft_batch batch, char* buf, size_t len)
+{
+    clear_error();
+    return batch_describe(batch, buf, len);
 }
 
 } // extern "C"

@@ -618,40 +618,44 @@ int build_plan(Plan& plan, unsigned /*flags*/)
     for (const Pass& q : plan.fwd) fwd_uses_ws |= (q.src == B_WS || q.dst == B_WS);
     plan.ws_bytes = (inv_uses_ws || fwd_uses_ws) ? half_bytes : 0;
 
-    // ---------------- Poisson (R2C plans): forward into A, multiply, inverse
-    // out of A.  Buffers: A = first half of the Poisson workspace, B = the
-    // second half (used when the plan runs transposed).
-    plan.poisson.clear();
-    plan.poisson_ws_bytes = 0;
-    if (real) {
-        auto remap = [](BufId b, BufId in, BufId out, BufId ws) {
-            return b == B_IN ? in : b == B_OUT ? out : b == B_WS ? ws : b;
-        };
-        // forward: IN -> A (its OUT), workspace B
-        for (Pass q : plan.fwd) {
-            q.src = remap(q.src, B_IN, B_SEND, B_RECV);
-            q.dst = remap(q.dst, B_IN, B_SEND, B_RECV);
-            plan.poisson.push_back(q);
-        }
-        Pass m;
-        m.kind = P_POISSON;
-        m.n0 = n0;
-        m.n1 = n1;
-        m.n2c = nc;
-        m.scale = 1.0 / ((double)n0 * n1 * n2);
-        m.src = m.dst = B_SEND;
-        plan.poisson.push_back(m);
-        // inverse: A -> ... -> OUT, workspace B
-        for (Pass q : plan.inv) {
-            q.src = remap(q.src, B_SEND, B_OUT, B_RECV);
-            q.dst = remap(q.dst, B_SEND, B_OUT, B_RECV);
-            plan.poisson.push_back(q);
-        }
-        plan.poisson_ws_bytes = 2 * half_bytes;
-        if (plan.poisson_ws_bytes > plan.ws_bytes) plan.default_ws_bytes = plan.poisson_ws_bytes;
-    }
+    rebuild_poisson(plan);
     if (plan.ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.ws_bytes;
     return MIFFT_OK;
+}
+
+// Poisson (R2C plans): forward into A, multiply, inverse out of A.  Buffers:
+// A = first half of the Poisson workspace, B = the second half (used when
+// the plan runs transposed).
+void rebuild_poisson(Plan& plan)
+{
+    plan.poisson.clear();
+    plan.poisson_ws_bytes = 0;
+    if (plan.kind != MIFFT_R2C) return;
+    const int nc = plan.n2 / 2 + 1;
+    const size_t half_bytes = (size_t)plan.n0 * plan.n1 * nc * plan.esz;
+    auto remap = [](BufId b, BufId in, BufId out, BufId ws) {
+        return b == B_IN ? in : b == B_OUT ? out : b == B_WS ? ws : b;
+    };
+    for (Pass q : plan.fwd) { // IN -> A (its OUT), workspace B
+        q.src = remap(q.src, B_IN, B_SEND, B_RECV);
+        q.dst = remap(q.dst, B_IN, B_SEND, B_RECV);
+        plan.poisson.push_back(q);
+    }
+    Pass m;
+    m.kind = P_POISSON;
+    m.n0 = plan.n0;
+    m.n1 = plan.n1;
+    m.n2c = nc;
+    m.scale = 1.0 / ((double)plan.n0 * plan.n1 * plan.n2);
+    m.src = m.dst = B_SEND;
+    plan.poisson.push_back(m);
+    for (Pass q : plan.inv) { // A -> ... -> OUT, workspace B
+        q.src = remap(q.src, B_SEND, B_OUT, B_RECV);
+        q.dst = remap(q.dst, B_SEND, B_OUT, B_RECV);
+        plan.poisson.push_back(q);
+    }
+    plan.poisson_ws_bytes = 2 * half_bytes;
+    if (plan.poisson_ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.poisson_ws_bytes;
 }
 
 int build_pencil(Plan& plan, unsigned /*flags*/)

@@ -118,6 +118,7 @@ hipError_t launch_pass(const Pass& p, int prec, const void* src, void* dst, hipS
 int get_twiddles(Plan& plan, int L, void** out);
 
 int build_plan(Plan& plan, unsigned flags);
+void rebuild_poisson(Plan& plan); // re-derive the Poisson pass list from fwd / inv
 int build_pencil(Plan& plan, unsigned flags);
 
 } // namespace mifft

@@ -1,6 +1,234 @@
-// tune.hip -- autotuner (placeholder until the timing search is in place).
+// tune.hip -- MIFFT_TUNE: measure the compiled alternatives of every pass of a
+// plan and keep the fastest (planning by measurement, in the spirit of the
+// MEASURE planner the paper builds its libraries with, Sec. 3).
+//
+// For a contiguous or real pass the candidates are every compiled variant of
+// its line length (radix order, elements per thread) times the lines per
+// workgroup; for a strided pass, every variant times the column-tile width B.
+// Each candidate runs on scratch buffers of the plan's size, 2 untimed + 5
+// timed launches on a private stream, and the minimum time wins.  Choices are
+// kept in a process-wide wisdom table keyed by device architecture,
+// precision, pass kind and geometry; when MIFFT_WISDOM names a file the table
+// is loaded from it once and written back (atomically) after every tuning,
+// so a restarted process reuses tuned plans without timing them again.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "plan.hpp"
 
 namespace mifft {
-int tune_plan(Plan&) { return MIFFT_OK; }
+
+struct Choice {
+    int policy, emul, B, lpw;
+    double us;
+};
+
+static std::mutex g_wmu;
+static std::map<std::string, Choice> g_wisdom;
+static bool g_wisdom_loaded = false;
+
+static const char* wisdom_path() { return getenv("MIFFT_WISDOM"); }
+
+// One entry per line:  "key": [policy, emul, B, lpw, microseconds],
+static void load_wisdom_locked()
+{
+    if (g_wisdom_loaded) return;
+    g_wisdom_loaded = true;
+    const char* path = wisdom_path();
+    if (!path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t a = line.find('"'), b = line.find('"', a + 1), c = line.find('[', b);
+        if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
+        Choice ch;
+        if (sscanf(line.c_str() + c, "[%d, %d, %d, %d, %lf]", &ch.policy, &ch.emul, &ch.B, &ch.lpw, &ch.us) == 5)
+            g_wisdom[line.substr(a + 1, b - a - 1)] = ch;
+    }
+}
+
+static void save_wisdom_locked()
+{
+    const char* path = wisdom_path();
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        f << "{\n";
+        size_t i = 0;
+        for (const auto& kv : g_wisdom) {
+            char buf[128];
+            snprintf(buf, sizeof(buf), "[%d, %d, %d, %d, %.3f]", kv.second.policy, kv.second.emul, kv.second.B,
+                     kv.second.lpw, kv.second.us);
+            f << "  \"" << kv.first << "\": " << buf << (++i < g_wisdom.size() ? ",\n" : "\n");
+        }
+        f << "}\n";
+    }
+    std::rename(tmp.c_str(), path);
+}
+
+static std::string pass_key(const Plan& plan, const Pass& p, const char* arch)
+{
+    static const char* kn[] = {"contig", "contig_pack", "strided", "strided_unpack", "r2c_z",
+                               "c2r_z",  "poisson",     "pack",    "unpack",         "copy"};
+    std::ostringstream k;
+    k << arch << "|" << (plan.prec == MIFFT_FP64 ? "fp64" : "fp32") << "|" << kn[p.kind] << "|L=" << p.L;
+    if (p.kind == P_STRIDED || p.kind == P_STRIDED_SPLIT)
+        k << "|cols=" << p.cols << "|groups=" << p.groups << "|es=" << p.es_in << "/" << p.es_out
+          << "|gs=" << p.gs_in << "/" << p.gs_out;
+    else
+        k << "|lines=" << p.nlines;
+    return k.str();
+}
+
+static bool is_tunable(const Pass& p)
+{
+    return p.kind == P_CONTIG || p.kind == P_STRIDED || p.kind == P_R2C || p.kind == P_C2R;
+}
+
+static int lds_len_of(const Pass& p)
+{
+    return (p.kind == P_R2C || p.kind == P_C2R) ? lds_padded_len(p.L + 1) : lds_padded_len(p.L);
+}
+
+// Re-shape pass p for (variant, B or lpw), keeping its buffers and strides.
+static bool apply_choice(const Plan& plan, Pass& p, int vidx, int shape)
+{
+    const int tpl = variant_tpl(plan.prec, vidx);
+    const size_t esz = plan.esz;
+    if (p.kind == P_STRIDED) {
+        const int B = shape;
+        if ((long long)B * tpl > 1024 || (size_t)B * p.L * esz > 160 * 1024) return false;
+        int lg = 0;
+        while ((1 << lg) < B) ++lg;
+        p.vidx = vidx;
+        p.B = B;
+        p.log2B = lg;
+        p.tiles_per_group = (p.cols + B - 1) / B;
+        p.grid = (unsigned)((long long)p.tiles_per_group * p.groups);
+        p.block = (unsigned)(B * tpl);
+        p.shmem = (size_t)B * p.L * esz;
+        return true;
+    }
+    const int lpw = shape;
+    if ((long long)lpw * tpl > 1024 || (size_t)lpw * lds_len_of(p) * esz > 160 * 1024) return false;
+    const int ni = p.ni;
+    const long long is_o = p.is_o, is_i = p.is_i, os_o = p.os_o, os_i = p.os_i;
+    p.vidx = vidx;
+    p.lines_per_wg = lpw;
+    p.grid = (unsigned)((p.nlines + lpw - 1) / lpw);
+    p.block = (unsigned)(lpw * tpl);
+    p.shmem = (size_t)lpw * lds_len_of(p) * esz;
+    set_line_map(p, ni, is_o, is_i, os_o, os_i);
+    return true;
+}
+
+static std::vector<std::pair<int, int>> candidates(const Plan& plan, const Pass& p)
+{
+    std::vector<std::pair<int, int>> out;
+    const int Lv = (p.kind == P_R2C || p.kind == P_C2R) ? p.L : p.L;
+    for (int v = 0; v < variant_count(plan.prec); ++v) {
+        if (variant_L(plan.prec, v) != Lv) continue;
+        const int tpl = variant_tpl(plan.prec, v);
+        if (p.kind == P_STRIDED) {
+            for (int B : {4, 8, 16, 32, 64})
+                if ((long long)B * tpl >= 64 || B == 64) out.push_back({v, B});
+        } else {
+            for (int lpw : {1, 2, 4, 8, 16, 32})
+                if ((long long)lpw * tpl >= 64 || lpw == 32) out.push_back({v, lpw});
+        }
+    }
+    return out;
+}
+
+int tune_plan(Plan& plan)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, plan.device) != hipSuccess)
+        return set_error(MIFFT_ERR_DEVICE, "tuning: device properties");
+    char arch[64];
+    snprintf(arch, sizeof(arch), "%.*s", 6, prop.gcnArchName);
+    std::lock_guard<std::mutex> g(g_wmu);
+    load_wisdom_locked();
+
+    const size_t nc = plan.kind == MIFFT_R2C ? plan.n2 / 2 + 1 : plan.n2;
+    const size_t cbytes = (size_t)plan.n0 * plan.n1 * nc * plan.esz;
+    const size_t rbytes = (size_t)plan.n0 * plan.n1 * plan.n2 * plan.esz / 2;
+    const size_t bytes = std::max(cbytes, rbytes) + 256;
+    void *A = nullptr, *B = nullptr, *W = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = MIFFT_OK;
+    bool tuned_any = false;
+    if (hipMalloc(&A, bytes) != hipSuccess || hipMalloc(&B, bytes) != hipSuccess ||
+        hipMalloc(&W, bytes) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = set_error(MIFFT_ERR_NOMEM, "tuning scratch buffers");
+    } else {
+        hipMemsetAsync(A, 0, bytes, s);
+        hipMemsetAsync(B, 0, bytes, s);
+        hipMemsetAsync(W, 0, bytes, s);
+        auto buf = [&](BufId b) -> void* { return b == B_IN ? A : b == B_WS ? W : B; };
+        for (auto* list : {&plan.fwd, &plan.inv}) {
+            for (Pass& p : *list) {
+                if (!is_tunable(p)) continue;
+                const std::string key = pass_key(plan, p, arch);
+                auto it = g_wisdom.find(key);
+                if (it != g_wisdom.end()) {
+                    const int v = find_variant(plan.prec, p.L, it->second.policy, it->second.emul);
+                    if (v >= 0 && apply_choice(plan, p, v, p.kind == P_STRIDED ? it->second.B : it->second.lpw))
+                        continue;
+                }
+                Choice best{-1, -1, 0, 0, 1e30};
+                Pass best_pass = p;
+                for (auto [v, shape] : candidates(plan, p)) {
+                    Pass q = p;
+                    if (!apply_choice(plan, q, v, shape)) continue;
+                    bool ok = true;
+                    for (int w = 0; w < 2 && ok; ++w)
+                        ok = launch_pass(q, plan.prec, buf(q.src), buf(q.dst), s) == hipSuccess;
+                    hipEventRecord(e0, s);
+                    for (int r = 0; r < 5 && ok; ++r)
+                        ok = launch_pass(q, plan.prec, buf(q.src), buf(q.dst), s) == hipSuccess;
+                    hipEventRecord(e1, s);
+                    if (!ok || hipEventSynchronize(e1) != hipSuccess) {
+                        (void)hipGetLastError();
+                        continue;
+                    }
+                    float ms = 0;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    const double us = ms * 1e3 / 5;
+                    if (us < best.us) {
+                        best = Choice{variant_policy(plan.prec, v), variant_emul(plan.prec, v),
+                                      q.kind == P_STRIDED ? q.B : 0, q.kind == P_STRIDED ? 0 : q.lines_per_wg, us};
+                        best_pass = q;
+                    }
+                }
+                if (best.policy >= 0) {
+                    p = best_pass;
+                    g_wisdom[key] = best;
+                    tuned_any = true;
+                }
+            }
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) rc = set_error(MIFFT_ERR_DEVICE, "tuning run failed");
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (s) hipStreamDestroy(s);
+    if (A) hipFree(A);
+    if (B) hipFree(B);
+    if (W) hipFree(W);
+    if (tuned_any) save_wisdom_locked();
+    if (rc == MIFFT_OK) rebuild_poisson(plan);
+    return rc;
+}
+
 } // namespace mifft

@@ -23,6 +23,8 @@ draws rounded to nearest):
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 UNEVEN_SHAPES = ((48, 48, 48), (64, 64, 64), (96, 96, 96), (128, 128, 128),
@@ -124,3 +126,25 @@ def arrival_schedule(count: int, rate: float, seed: int = 0, sizes=SERVE_SIZES,
     n = rng.choice(np.asarray(sizes), size=count)
     fp32 = rng.random(size=count) < fp32_fraction
     return [(float(t[i]), int(n[i]), "fp32" if fp32[i] else "fp64") for i in range(count)]
+
+
+def poisson_rhs_torch(n: int, seed: int, dtype, device, noise: float = 0.01):
+    """The Poisson right-hand side recipe evaluated on the device: the same 8
+    seeded modes as ``poisson_modes``, summed in float64, plus N(0, noise^2)
+    noise from a torch generator seeded with ``seed``; cast to ``dtype``.
+    Used where host generation of large grids would stall the caller; the
+    values are copied back whenever a CPU check needs them."""
+    import torch
+    ks, amp, phase, _ = poisson_modes(n, seed)
+    x = 2.0 * math.pi * torch.arange(n, dtype=torch.float64, device=device) / n
+    out = torch.zeros((n, n, n), dtype=torch.float64, device=device)
+    for k, a, p in zip(ks, amp, phase):
+        ab = float(k[0]) * x[:, None] + float(k[1]) * x[None, :] + float(p)
+        c = float(k[2]) * x
+        out += float(a) * (torch.cos(ab)[:, :, None] * torch.cos(c)[None, None, :]
+                           - torch.sin(ab)[:, :, None] * torch.sin(c)[None, None, :])
+    if noise:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(seed))
+        out += noise * torch.randn((n, n, n), generator=g, dtype=torch.float64, device=device)
+    return out.to(dtype)

@@ -128,3 +128,24 @@ def test_package_exports_load_the_library():
     assert pkg.PencilPlan.__name__ == "PencilPlan"
     assert issubclass(pkg.MifftError, RuntimeError)
     from paper_1506_07933_amd import Plan  # noqa: F401
+
+
+def test_batch_argument_validation(L):
+    import ctypes as C
+    h = C.c_void_p()
+    dims = (C.c_int * 6)(64, 64, 64, 48, 48, 48)
+    assert L.mifft_batch_create(None, 2, dims, 0, 0, 0) == 1
+    assert L.mifft_batch_create(C.byref(h), 0, dims, 0, 0, 0) == 1
+    assert L.mifft_batch_create(C.byref(h), 2, dims, 1, 0, 0) == 2      # R2C batches not offered
+    assert L.mifft_batch_create(C.byref(h), 2, dims, 0, 0, 0x100) == 1  # unknown flag
+    big = (C.c_int * 6)(512, 64, 64, 48, 48, 48)
+    assert L.mifft_batch_create(C.byref(h), 2, big, 0, 0, 0) == 2       # 512 not in the menu
+    assert L.mifft_batch_create(C.byref(h), 129, (C.c_int * 387)(*([8] * 387)), 0, 0, 0) == 2
+    ones = (C.c_int * 6)(1, 1, 1, 48, 48, 48)
+    assert L.mifft_batch_create(C.byref(h), 2, ones, 0, 0, 0) == 2     # 1x1x1 has no pass
+    bogus = C.c_void_p(0x4321000)
+    arr = (C.c_void_p * 2)()
+    assert L.mifft_batch_execute_forward(bogus, arr, arr, None) == 5
+    assert L.mifft_batch_destroy(bogus) == 5
+    flag = C.c_int()
+    assert L.mifft_batch_check(bogus, C.byref(flag)) == 5
