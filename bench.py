@@ -77,12 +77,90 @@ def copy_mode(args):
                       "ms": ms, "GBps": 16 * n / ms / 1e6}), flush=True)
 
 
+def _timer(torch):
+    def time_fn(fn, warmup, steps):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+    return time_fn
+
+
+def secondary(torch, np, steps):
+    """Short measurements of the other workloads (context for the headline)."""
+    from paper_1506_07933_amd import BatchPlan, PencilPlan, Plan, serve, synth
+    time_fn = _timer(torch)
+    out = {}
+    # plain single-transform FP64 path at the headline size
+    x = torch.from_numpy(synth.uniform_complex((512, 512, 512), np.complex128, seed=0)).cuda()
+    y = torch.empty_like(x)
+    p = Plan((512, 512, 512), "c2c", "fp64")
+    ms = time_fn(lambda: p.forward(x, out=y), 2, max(3, steps // 4))
+    out["c2c_512cube_fp64_forward"] = {"ms": round(ms, 4), "alg_GBps": round(48 * 2 * 512 ** 3 / ms / 1e6, 1)}
+    p.close()
+    del x, y
+    # 256^3 R2C / C2R, FP64 and FP32
+    for prec, rd, cd in (("fp64", np.float64, torch.complex128), ("fp32", np.float32, torch.complex64)):
+        xr = torch.from_numpy(synth.normal_real((256, 256, 256), rd, seed=0)).cuda()
+        p = Plan((256, 256, 256), "r2c", prec)
+        Y = torch.empty((256, 256, 129), dtype=cd, device="cuda")
+        xo = torch.empty_like(xr)
+        f = time_fn(lambda: p.forward(xr, out=Y), 2, steps)
+        i = time_fn(lambda: p.inverse(Y, out=xo), 2, steps)
+        esz = 8 if prec == "fp64" else 4
+        alg = 256 ** 3 * esz + 5 * 256 * 256 * 129 * 2 * esz
+        out["r2c_256cube_" + prec] = {"forward_ms": round(f, 4), "inverse_ms": round(i, 4),
+                                      "forward_alg_GBps": round(alg / f / 1e6, 1)}
+        p.close()
+    # one GPU's pencil share of a 1024^3 transform on a 4x4 grid
+    pp = PencilPlan((1024, 1024, 1024), (4, 4), "fp32")
+    a = torch.from_numpy(synth.uniform_complex(pp.local_shape, np.complex64, seed=0)).cuda()
+    send = torch.empty(pp.send_shape, dtype=torch.complex64, device="cuda")
+    ob = torch.empty(pp.out_shape, dtype=torch.complex64, device="cuda")
+    nl = a.numel()
+    fused = time_fn(lambda: pp.forward_share(a, send, ob, fused=True), 2, steps)
+    unfused = time_fn(lambda: pp.forward_share(a.clone(), send, ob, fused=False), 1, max(3, steps // 4))
+    out["pencil_share_256x256x1024_fp32"] = {
+        "fused_ms": round(fused, 4), "fused_alg_GBps": round(32 * nl / fused / 1e6, 1),
+        "unfused_ms_incl_input_copy": round(unfused, 4)}
+    pp.close()
+    del a, send, ob
+    # 64 uneven transforms in one persistent graph launch vs per-pass kernels
+    shapes, data = synth.batched_uneven(64, seed=0, dtype=np.complex64)
+    xs = [torch.from_numpy(d).cuda() for d in data]
+    outs = [torch.empty_like(v) for v in xs]
+    nb = sum(v.numel() for v in xs)
+    bp = BatchPlan(shapes, "fp32")
+    g = time_fn(lambda: bp.forward(xs, outs, graph=True), 2, steps)
+    assert not bp.aborted()
+    bk = BatchPlan(shapes, "fp32", mode="kernels")
+    k = time_fn(lambda: bk.forward(xs, outs), 2, steps)
+    out["batched_64_uneven_fp32"] = {"persistent_graph_ms": round(g, 4), "per_pass_kernels_ms": round(k, 4),
+                                     "elements": nb, "persistent_alg_GBps": round(48 * nb / g / 1e6, 1)}
+    bp.close()
+    bk.close()
+    del xs, outs
+    # served Poisson solves: a short open-loop replay
+    s, recs, ex = serve.serve(n_requests=300, rate=200.0, seed=0, slots=4, budget_gb=32.0)
+    ex.close()
+    out["served_poisson"] = {k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in s.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--mode", choices=["fft", "copy"], default="fft")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -105,6 +183,7 @@ def main():
     y = torch.empty_like(x)
     plan = Plan((N0, N1, N2), "c2c", "fp32")
     passes = [l for l in plan.describe().splitlines() if l.startswith("forward")]
+    axes = [l.split("axis=")[1][0] for l in passes]
 
     for _ in range(args.warmup):
         plan.forward(x, out=y)
@@ -120,16 +199,25 @@ def main():
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    pass_ms, ncalls = profile_end(plan.handle)
+    pass_ms, ncalls = profile_end(plan.handle, max_passes=64)
     ms = start.elapsed_time(stop) / args.steps
+
+    # a plain device copy of the same 1 GiB, for context
+    cpy = torch.empty_like(x)
+    copy_ms = _timer(torch)(lambda: cpy.copy_(x), 2, 10)
+    del cpy
 
     total_bytes = 3 * 16 * n  # 48 N: each pass reads and writes every complex64 once
     value = total_bytes / (ms * 1e-3) / 1e9
-    names = ["z_contig", "y_strided", "x_strided"]
-    dom = int(np.argmax(pass_ms))
-    kbytes = 16 * n  # one pass: read + write of N complex64
-    achieved = kbytes / (pass_ms[dom] * 1e-3) / 1e9
-    kname = {0: "k_contig", 1: "k_strided(y)", 2: "k_strided(x)"}[dom]
+    kbytes = 16 * n  # one axis pass: read + write of N complex64
+    per_axis = {}
+    for a, t in zip(axes, pass_ms):
+        per_axis[a] = per_axis.get(a, 0.0) + t
+    names = {"z": "z_contig", "y": "y_strided", "x": "x_strided"}
+    dom = max(per_axis, key=per_axis.get)
+    launches = sum(1 for a in axes if a == dom)
+    achieved = kbytes / (per_axis[dom] * 1e-3) / 1e9
+    kname = {"z": "k_contig", "y": "k_strided(y, transposing)", "x": "k_strided(x)"}[dom]
     traffic = load_traffic(names[dom], kbytes)
     out = {
         "metric": "3-D FFT time & HBM GB/s vs peak (512^3 C2C fp32)",
@@ -149,15 +237,18 @@ def main():
                    "placement": "out of place, input resident in HBM"},
         "gflops_5nlog2n": round(5 * n * math.log2(n) / (ms * 1e-3) / 1e9, 1),
         "frac_of_hbm_peak": round(value / PEAK_HBM_GBS, 4),
+        "device_copy_GBps": round(2 * 8 * n / (copy_ms * 1e-3) / 1e9, 1),
+        "frac_of_device_copy": round(value / (2 * 8 * n / (copy_ms * 1e-3) / 1e9), 4),
         "wall_ms_per_step": round(wall * 1e3 / args.steps, 5),
-        "passes": [{"pass": names[i], "ms": round(pass_ms[i], 5),
-                    "alg_GBps": round(kbytes / (pass_ms[i] * 1e-3) / 1e9, 1)}
-                   for i in range(len(pass_ms))],
+        "passes": [{"pass": names[a], "ms": round(per_axis[a], 5), "launches": axes.count(a),
+                    "alg_GBps": round(kbytes / (per_axis[a] * 1e-3) / 1e9, 1)} for a in "zyx"
+                   if a in per_axis],
         "plan": passes,
         "roofline": {"bound": "hbm", "kernel": kname + " " + names[dom],
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": kbytes, "launches_timed": ncalls},
+                     "alg_bytes_per_axis_pass": kbytes, "launches_per_step": launches,
+                     "steps_timed": ncalls},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -167,12 +258,17 @@ def main():
         t_cpu = time.perf_counter() - t0
         got = y.cpu().numpy().astype(np.complex128)
         rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        del ref, got
         out["cpu_baseline"] = {"value": round(total_bytes / t_cpu / 1e9, 3), "unit": "GB/s",
                                "cores": oracle.max_threads(), "kind": "oracle",
                                "sample": "one full 512^3 forward transform of the same input, "
                                          "FP64, %.1f s" % t_cpu}
         out["rel_l2_vs_oracle"] = rel
     plan.close()
+    del x, y
+    if not args.no_secondary:
+        torch.cuda.empty_cache()
+        out["secondary"] = secondary(torch, np, args.steps)
     print(json.dumps(out), flush=True)
 
 

@@ -10,6 +10,7 @@
 // per distinct shape), which also covers lengths outside the persistent
 // kernel's menu.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -40,6 +41,7 @@ struct mifft_batch_s {
     int* d_counters = nullptr;
     int ncounters = 0;
     int total_items = 0;
+    int stage_items[mifft::kBatchStages] = {0, 0, 0};
     unsigned grid = 0;
     size_t lds = 0;
     std::map<int, void*> tw;
@@ -151,6 +153,12 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
         std::vector<BatchPass>& P = b->passes;
         std::vector<int> last(count, -1); // index of each transform's latest pass
         size_t max_wave_lds = 0;
+        // data per queue item (MIFFT_BATCH_ITEM_KIB overrides the 64 KiB default)
+        size_t item_bytes = 64 * 1024;
+        if (const char* e = getenv("MIFFT_BATCH_ITEM_KIB")) {
+            const long v = atol(e);
+            if (v > 0 && v <= 64 * 1024) item_bytes = (size_t)v * 1024;
+        }
         for (int stage = 0; stage < 3; ++stage) {
             for (int t = 0; t < count; ++t) {
                 const int n0 = dims[3 * t], n1 = dims[3 * t + 1], n2 = dims[3 * t + 2];
@@ -182,14 +190,16 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
                     p.subtiles = p.subtiles_per_group;
                     p.units = p.cols;
                 }
-                // queue items of ~64 KiB of data, a multiple of the wavefronts per workgroup
+                // queue items of ~item_bytes of data, a multiple of the wavefronts per workgroup
                 const size_t sub_bytes = (size_t)p.per_wave * L * esz;
-                int spi = (int)((65536 + sub_bytes * kBatchWaves - 1) / (sub_bytes * kBatchWaves)) * kBatchWaves;
+                int spi = (int)((item_bytes + sub_bytes * kBatchWaves - 1) / (sub_bytes * kBatchWaves)) * kBatchWaves;
                 spi = std::max(kBatchWaves, std::min(spi, ((p.subtiles + kBatchWaves - 1) / kBatchWaves) * kBatchWaves));
                 p.sub_per_item = spi;
                 p.nitems = (p.subtiles + spi - 1) / spi;
+                p.stage = stage;
                 p.dep = last[t];
                 p.dep_target = last[t] >= 0 ? P[last[t]].nitems : 0;
+                p.dep_stage = last[t] >= 0 ? P[last[t]].stage : 0;
                 p.done = (int)P.size();
                 auto it = b->tw.find(L);
                 if (it == b->tw.end()) {
@@ -217,9 +227,10 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
         for (BatchPass& p : P) {
             p.item_start = start;
             start += p.nitems;
+            b->stage_items[p.stage] += p.nitems;
         }
         b->total_items = start;
-        b->ncounters = (int)P.size() + 2;
+        b->ncounters = (int)P.size() + 2 + kBatchStages;
         b->lds = max_wave_lds * esz * kBatchWaves;
         if (hipMalloc(&b->d_passes, sizeof(BatchPass) * P.size()) != hipSuccess ||
             hipMalloc(&b->d_counters, sizeof(int) * b->ncounters) != hipSuccess) {
@@ -270,6 +281,7 @@ static int enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t
         a.total_items = b->total_items;
         a.counters = b->d_counters;
         a.spin_limit = 1u << 22;
+        for (int k = 0; k < kBatchStages; ++k) a.stage_items[k] = b->stage_items[k];
         for (int t = 0; t < b->count; ++t) {
             a.in[t] = (const cx<double>*)in[t];
             a.out[t] = (cx<double>*)out[t];
@@ -282,6 +294,7 @@ static int enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t
         a.total_items = b->total_items;
         a.counters = b->d_counters;
         a.spin_limit = 1u << 22;
+        for (int k = 0; k < kBatchStages; ++k) a.stage_items[k] = b->stage_items[k];
         for (int t = 0; t < b->count; ++t) {
             a.in[t] = (const cx<float>*)in[t];
             a.out[t] = (cx<float>*)out[t];
@@ -355,7 +368,7 @@ int batch_check(mifft_batch b, int* aborted)
     *aborted = 0;
     if (b->kernels) return MIFFT_OK;
     int flag = 0;
-    hipError_t e = hipMemcpy(&flag, b->d_counters + b->ncounters - 1, sizeof(int), hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(&flag, b->d_counters + 1 + b->passes.size(), sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "reading the abort flag: %s", hipGetErrorString(e));
     *aborted = flag;
     return MIFFT_OK;

@@ -2,14 +2,28 @@
 // uneven sizes.
 //
 // Every (transform, pass) of the batch is a run of work items; the items of
-// all z-passes come first in the queue, then all y-passes, then all
-// x-passes.  Persistent workgroups take items from a device counter in
-// queue order.  An item of a y- or x-pass first waits until every item of
-// the same transform's previous pass has completed (a per-pass completion
-// counter).  Because an item only ever waits for items that sit earlier in
-// the queue, and those were taken by workgroups that are already running
-// and never wait on anything later, the queue always drains, whether or not
-// all workgroups are resident.  Every wait is bounded as well: a wait that
+// all z-passes come first in the queue (stage 0), then all y-passes (stage
+// 1), then all x-passes (stage 2).  Persistent workgroups take items from a
+// device counter in queue order.  An item of a y- or x-pass first waits
+// until every item of the same transform's previous pass has completed (a
+// per-pass completion counter).
+//
+// Completions are published lazily: a workgroup collects the items it has
+// finished in a short pending list and publishes them (one release of its
+// stores, then one counter update per pass and one per stage) only before
+// it waits for anything, when the stage of its next item differs from the
+// pending one, when the list is full, and when it leaves.  On this chip an
+// agent-scope release writes back the XCD's L2 and an acquire invalidates
+// it, so doing both per item would dominate the run; batched, a workgroup
+// publishes a few times per stage.  Acquires are likewise skipped for a
+// dependency already acquired, and for every pass of a stage that was seen
+// complete before the workgroup's last acquire.
+//
+// The queue always drains: an item only waits for items that sit earlier in
+// the queue, taken by workgroups that are running; a workgroup publishes
+// everything it holds before it waits, so a holder either publishes on its
+// way to its next wait or keeps taking items until the queue is empty and
+// leaves, publishing then.  Every wait is bounded as well: a wait that
 // exceeds its bound raises an abort flag that makes every workgroup leave.
 //
 // Inside an item each wavefront transforms its own lines (z) or its own
@@ -27,6 +41,8 @@ namespace mifft {
 constexpr int kBatchMax = 128;      // transforms per batch (pointer slots in the kernel args)
 constexpr int kBatchBlock = 256;    // threads per workgroup (4 wavefronts)
 constexpr int kBatchWaves = kBatchBlock / 64;
+constexpr int kBatchStages = 3;     // z, y, x
+constexpr int kBatchPend = 16;      // passes in a workgroup's pending completion list
 
 // Line lengths with a code path in the persistent kernel: every length up to
 // 256 with prime factors 2, 3, 5 whose threads per line fit one wavefront.
@@ -54,8 +70,10 @@ struct BatchPass {
     int item_start;      // first queue index of this pass
     int cols;            // kind 1: columns per group
     long long gs, es;    // kind 1: group and element strides
+    int stage;           // 0 z, 1 y, 2 x (queue order)
     int dep;             // completion counter to wait for, -1: none
     int dep_target;      // items it must reach
+    int dep_stage;       // stage of that pass
     int done;            // completion counter of this pass
     const void* tw;      // twiddles of length L
 };
@@ -64,8 +82,11 @@ template <typename T> struct BatchArgs {
     const BatchPass* passes;
     int npass;
     int total_items;
-    int* counters;       // [0] queue head, [1 + p] completion of pass p, [1 + npass] abort flag
-    unsigned spin_limit; // bound on the polls of one wait
+    // [0] queue head, [1 + p] completion of pass p, [1 + npass] abort flag,
+    // [2 + npass + s] completion of stage s
+    int* counters;
+    int stage_items[kBatchStages]; // items per stage
+    unsigned spin_limit;           // bound on the polls of one wait
     const cx<T>* in[kBatchMax];
     cx<T>* out[kBatchMax];
 };
@@ -263,23 +284,64 @@ __device__ __forceinline__ int batch_dequeue(int* head, int* abort_flag, int tot
     return __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Publish the pending completions of this workgroup (all threads call it,
+// under a uniform condition).  Every wavefront waits for its own stores and
+// releases them at agent scope; after the barrier thread 0 releases once more
+// and adds the counts.
+//
+// The explicit wait after each release makes the L2 write-back complete
+// before the barrier / the counter updates: the compiler drops its own wait
+// after the write-back when no other vector memory operation is outstanding.
+__device__ __forceinline__ void batch_release_agent()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+__device__ __forceinline__ void batch_publish(int* pass_done, int* stage_done, int pend_stage, int* s_npend,
+                                              const int* s_pend_ctr, const int* s_pend_n)
+{
+    batch_release_agent();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        batch_release_agent();
+        int total = 0;
+        for (int i = 0; i < *s_npend; ++i) {
+            __hip_atomic_fetch_add(pass_done + s_pend_ctr[i], s_pend_n[i], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            total += s_pend_n[i];
+        }
+        __hip_atomic_fetch_add(stage_done + pend_stage, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *s_npend = 0;
+    }
+    __syncthreads();
+}
+
 // Loop structure: every region that only thread 0 executes (the dequeue, the
-// dependency wait, the release and completion count) sits between two
-// workgroup barriers, and the loop's back edge leaves from a barrier.  With a
-// thread-0 region at the end of one iteration and another at the start of
-// the next, the compiler may merge them across the back edge and let the
-// other lanes run the next iteration's barrier before thread 0 has
-// published the next item.
+// dependency check and wait, the pending list) sits between two workgroup
+// barriers, and the loop's back edge leaves from a barrier.  With a thread-0
+// region at the end of one iteration and another at the start of the next,
+// the compiler may merge them across the back edge and let the other lanes
+// run the next iteration's barrier before thread 0 has published the next
+// item.  Decisions thread 0 takes reach the other threads through LDS.
 template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchArgs<T> a)
 {
     using V = cx<T>;
-    __shared__ int s_item, s_abort;
+    __shared__ int s_item, s_abort, s_flush, s_need, s_full, s_npend;
+    __shared__ int s_pend_ctr[kBatchPend], s_pend_n[kBatchPend];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int* head = a.counters;
+    int* pass_done = a.counters + 1;
     int* abort_flag = a.counters + 1 + a.npass;
+    int* stage_done = a.counters + 2 + a.npass;
+    // thread 0's bookkeeping (registers of thread 0 only)
+    int pend_stage = -1; // stage of the pending completions
+    int acq_dep = -1;    // last dependency acquired after it had completed
+    int acq_stages = 0;  // stages seen complete before an acquire (bit mask)
     if (tid == 0) {
         s_item = batch_dequeue(head, abort_flag, a.total_items);
         s_abort = 0;
+        s_npend = 0;
     }
     __syncthreads();
     for (int iter = 0;; ++iter) {
@@ -299,8 +361,6 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
             else hi = mid - 1;
         }
         const BatchPass* pp = a.passes + lo;
-        const int dep = __builtin_amdgcn_readfirstlane(pp->dep);
-        const int dep_target = __builtin_amdgcn_readfirstlane(pp->dep_target);
         const int code = __builtin_amdgcn_readfirstlane(pp->code);
         const int from_in = __builtin_amdgcn_readfirstlane(pp->from_in);
         const int xform = __builtin_amdgcn_readfirstlane(pp->xform);
@@ -308,12 +368,27 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
         const int spi = __builtin_amdgcn_readfirstlane(pp->sub_per_item);
         const int subtiles = __builtin_amdgcn_readfirstlane(pp->subtiles);
         const int wl = __builtin_amdgcn_readfirstlane(batch_wave_lds(pp->L, pp->tpl));
-        const int done = __builtin_amdgcn_readfirstlane(pp->done);
-        if (dep >= 0) {
+        // 1. thread 0: does this item need an acquire, is its dependency
+        //    complete, must the pending completions be published first?
+        if (tid == 0) {
+            const int dep = pp->dep, stage = pp->stage, done = pp->done;
+            const int need = dep >= 0 && dep != acq_dep && !((acq_stages >> pp->dep_stage) & 1);
+            const int ready =
+                !need || __hip_atomic_load(pass_done + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pp->dep_target;
+            int listed = 0;
+            for (int i = 0; i < s_npend; ++i) listed |= s_pend_ctr[i] == done;
+            s_need = need;
+            s_flush = s_npend > 0 && (!ready || stage != pend_stage || (s_npend == kBatchPend && !listed));
+        }
+        __syncthreads();
+        // 2. publish
+        if (__builtin_amdgcn_readfirstlane(s_flush)) batch_publish(pass_done, stage_done, pend_stage, &s_npend, s_pend_ctr, s_pend_n);
+        // 3. wait for the dependency and acquire
+        if (__builtin_amdgcn_readfirstlane(s_need)) {
             if (tid == 0) {
+                const int dep = pp->dep, target = pp->dep_target, ds = pp->dep_stage;
                 unsigned polls = 0;
-                while (__hip_atomic_load(a.counters + 1 + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                       dep_target) {
+                while (__hip_atomic_load(pass_done + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                     if (++polls > a.spin_limit ||
                         __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                         __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -322,7 +397,13 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
                     }
                     __builtin_amdgcn_s_sleep(4);
                 }
+                // read before the acquire: a stage complete now is covered by it
+                const int st_items = ds == 0 ? a.stage_items[0] : (ds == 1 ? a.stage_items[1] : a.stage_items[2]);
+                const int full =
+                    __hip_atomic_load(stage_done + ds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= st_items;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                acq_dep = dep;
+                if (full) acq_stages |= 1 << ds;
             }
             __syncthreads();
             if (__builtin_amdgcn_readfirstlane(s_abort)) break;
@@ -339,17 +420,26 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
         const int first = (item - item_start) * spi;
         const int last = first + spi < subtiles ? first + spi : subtiles;
         batch_dispatch<T>(code, pp, src, dst, first, last, wave, lane, wlds);
-        // every wavefront releases its own stores at agent scope (waits for
-        // them and writes the L2 back) before the completion is counted
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // 4. thread 0: note the completion, take the next item
         __syncthreads();
         if (tid == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_fetch_add(a.counters + 1 + done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int done = pp->done;
+            int i = 0;
+            while (i < s_npend && s_pend_ctr[i] != done) ++i;
+            if (i == s_npend) {
+                s_pend_ctr[i] = done;
+                s_pend_n[i] = 0;
+                s_npend = i + 1;
+            }
+            s_pend_n[i] += 1;
+            pend_stage = pp->stage;
             s_item = batch_dequeue(head, abort_flag, a.total_items);
         }
         __syncthreads(); // the next item is published
     }
+    // publish what is left (the loop leaves right after a barrier)
+    if (__builtin_amdgcn_readfirstlane(s_npend) > 0)
+        batch_publish(pass_done, stage_done, pend_stage, &s_npend, s_pend_ctr, s_pend_n);
 }
 
 // Zero the queue head, the completion counters and the abort flag (a kernel,

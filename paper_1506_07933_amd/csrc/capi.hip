@@ -242,7 +242,11 @@ static int run_passes(const Plan& cp, const std::vector<Pass>& list, const void*
             default: return nullptr;
             }
         };
-        hipError_t e = launch_pass(q, p.prec, res(q.src), res(q.dst), s);
+        char* src = (char*)res(q.src);
+        char* dst = (char*)res(q.dst);
+        if (src) src += q.off_in;
+        if (dst) dst += q.off_out;
+        hipError_t e = launch_pass(q, p.prec, src, dst, s);
         if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
         if (ev) hipEventRecord(ev[++qi], s);
     }
@@ -418,10 +422,11 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
         int pol = q.vidx >= 0 ? variant_policy(plan->prec, q.vidx) : -1;
         int tpl = q.vidx >= 0 ? variant_tpl(plan->prec, q.vidx) : 0;
         snprintf(line, sizeof(line),
-                 "%s kind=%s L=%d policy=%d tpl=%d sgn=%d lines=%lld lpw=%d B=%d cols=%d groups=%d "
-                 "es=%lld/%lld gs=%lld/%lld grid=%u block=%u lds=%zu\n",
-                 tag, kn[q.kind], q.L, pol, tpl, q.sgn, q.nlines, q.lines_per_wg, q.B, q.cols,
-                 q.groups, q.es_in, q.es_out, q.gs_in, q.gs_out, q.grid, q.block, q.shmem);
+                 "%s kind=%s axis=%c L=%d policy=%d tpl=%d sgn=%d lines=%lld lpw=%d B=%d cols=%d groups=%d "
+                 "es=%lld/%lld gs=%lld/%lld off=%lld/%lld grid=%u block=%u lds=%zu\n",
+                 tag, kn[q.kind], "zyx-"[q.tag < 3 ? q.tag : 3], q.L, pol, tpl, q.sgn, q.nlines, q.lines_per_wg,
+                 q.B, q.cols, q.groups, q.es_in, q.es_out, q.gs_in, q.gs_out, q.off_in, q.off_out, q.grid,
+                 q.block, q.shmem);
         s += line;
     };
     if (plan->pencil) {

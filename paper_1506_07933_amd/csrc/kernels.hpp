@@ -29,7 +29,7 @@ template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
     const V* __restrict__ in;
     V* __restrict__ out;
     V* lds;
-    const V* __restrict__ twd;
+    const V* twd; // twiddle table staged in LDS
     int t;
     bool valid;
     T sgn;           // +1 forward, -1 inverse (conjugate on load and store)
@@ -71,7 +71,7 @@ template <typename T, bool IN_SPLIT> struct StridedCtx {
     const V* __restrict__ in;
     V* __restrict__ out;
     V* lds; // column c of the tile: element idx at lds[idx * B]
-    const V* __restrict__ twd;
+    const V* twd; // twiddle table staged in LDS
     int t;
     int B;
     bool valid;
@@ -112,7 +112,7 @@ template <typename T, bool WAVE_LOCAL> struct R2CCtx {
     static constexpr bool kSyncAfterFirstRead = false;
     const V* __restrict__ in;
     V* lds;
-    const V* __restrict__ twd;
+    const V* twd; // twiddle table staged in LDS
     int t;
     bool valid;
     __device__ __forceinline__ V gload(int idx) const { return valid ? in[idx] : V{T(0), T(0)}; }
@@ -136,7 +136,7 @@ template <typename T, bool WAVE_LOCAL> struct C2RCtx {
     static constexpr bool kSyncAfterFirstRead = true;
     V* __restrict__ out; // the n2 reals of the line, as n2/2 pairs
     V* lds;
-    const V* __restrict__ twd;  // twiddles of the half length M
+    const V* twd;               // twiddles of the half length M, staged in LDS
     const V* __restrict__ twd2; // exp(-2 pi i k / n2), k = 0 .. M
     int t;
     int M;
@@ -191,6 +191,17 @@ template <int L, int TPL> constexpr bool wave_local() { return TPL <= 64 && (64 
 
 // ---------------------------------------------------------------- kernels
 
+// Copy the twiddle table of a line length into LDS (after the data tile):
+// the butterflies then read it through the LDS path instead of issuing
+// gathers through the vector memory path next to the data loads.
+template <typename T>
+__device__ __forceinline__ cx<T>* stage_twiddles(const cx<T>* __restrict__ tw, int L, cx<T>* dst)
+{
+    for (int i = threadIdx.x; i < L; i += blockDim.x) dst[i] = tw[i];
+    __syncthreads();
+    return dst;
+}
+
 // Line l of a batch sits at (l / ni) * s_o + (l % ni) * s_i on each side, so a
 // pass can read lines in one order and write them in another (the lines
 // themselves stay contiguous).
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(1024) void k_contig(ContigArgs<T> a)
     else
         c.out = a.out + lo * a.os_o + li * a.os_i;
     c.lds = smem + ln * lds_padded_len(L);
-    c.twd = a.tw;
+    c.twd = stage_twiddles<T>(a.tw, L, smem + a.lines_per_wg * lds_padded_len(L));
     c.t = tid - ln * TPL;
     c.sgn = a.sgn;
     c.pm = a.pm;
@@ -267,7 +278,7 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
     c.in = a.in + (long long)g * a.gs_in + col;
     c.out = a.out + (long long)g * a.gs_out + col;
     c.lds = smem + cc;
-    c.twd = a.tw;
+    c.twd = stage_twiddles<T>(a.tw, L, smem + a.B * L);
     c.t = t;
     c.B = a.B;
     c.sgn = a.sgn;
@@ -307,7 +318,7 @@ __global__ __launch_bounds__(1024) void k_r2c_z(RealArgs<T> a)
     const long long lo = line / a.ni, li = line - lo * a.ni;
     c.in = reinterpret_cast<const V*>(a.in) + lo * a.is_o + li * a.is_i;
     c.lds = smem + ln * lds_padded_len(L + 1);
-    c.twd = a.tw;
+    c.twd = stage_twiddles<T>(a.tw, L, smem + a.lines_per_wg * lds_padded_len(L + 1));
     c.t = tid - ln * TPL;
     LineFFT<T, L, TPL, decltype(c), typename RL<L, P>::type>::run(c);
     c.sync();
@@ -338,7 +349,7 @@ __global__ __launch_bounds__(1024) void k_c2r_z(RealArgs<T> a)
     c.valid = line < a.nlines;
     const long long lo = line / a.ni, li = line - lo * a.ni;
     c.lds = smem + ln * lds_padded_len(L + 1);
-    c.twd = a.tw;
+    c.twd = stage_twiddles<T>(a.tw, L, smem + a.lines_per_wg * lds_padded_len(L + 1));
     c.twd2 = a.tw2;
     c.t = tid - ln * TPL;
     c.M = L;

@@ -7,6 +7,7 @@
 // (or, for C2R, on the workspace, so the input is preserved).
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -158,9 +159,11 @@ static const size_t kLdsMax = 160 * 1024;
 void set_contig_geometry(Pass& p, int prec, int tpl, int L, long long nlines, int lds_len)
 {
     const size_t esz = prec == MIFFT_FP64 ? 16 : 8;
-    int lpw = 256 / tpl;
+    // ~128 threads per workgroup (several small workgroups per CU overlap their
+    // load, exchange and store phases)
+    int lpw = 128 / tpl;
     if (lpw < 1) lpw = 1;
-    while (lpw > 1 && (size_t)lpw * lds_len * esz > kLdsBudget) lpw /= 2;
+    while (lpw > 1 && ((size_t)lpw * lds_len + L) * esz > kLdsBudget) lpw /= 2;
     // keep enough workgroups to fill the chip when the batch is small
     while (lpw > 1 && lpw * tpl > 64 && (nlines + lpw - 1) / lpw < 1024) lpw /= 2;
     p.L = L;
@@ -168,7 +171,7 @@ void set_contig_geometry(Pass& p, int prec, int tpl, int L, long long nlines, in
     p.lines_per_wg = lpw;
     p.grid = (unsigned)((nlines + lpw - 1) / lpw);
     p.block = (unsigned)(lpw * tpl);
-    p.shmem = (size_t)lpw * lds_len * esz;
+    p.shmem = ((size_t)lpw * lds_len + L) * esz; // tiles + the staged twiddle table
     set_line_map(p, (int)(nlines > 0 ? nlines : 1), 0, L, 0, L);
 }
 
@@ -194,13 +197,13 @@ void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int group
     int B = 16;
     if (forceB > 0) {
         B = forceB;
-        while (B > 1 && ((size_t)B * tpl > 1024 || (size_t)B * L * esz > kLdsMax)) B /= 2;
-        while (B * tpl < 256 && B < 64 && (size_t)(2 * B) * L * esz <= kLdsBudget) B *= 2;
+        while (B > 1 && ((size_t)B * tpl > 1024 || (size_t)(B + 1) * L * esz > kLdsMax)) B /= 2;
+        while (B * tpl < 256 && B < 64 && (size_t)(2 * B + 1) * L * esz <= kLdsBudget) B *= 2;
         int cp = 1 << ilog2(cols < 1 ? 1 : cols);
         if (cp < B) B = cp;
     } else {
         while (B * tpl < 256 && B < 64) B *= 2;
-        while (B > 1 && ((size_t)B * tpl > 1024 || (size_t)B * L * esz > kLdsBudget)) B /= 2;
+        while (B > 1 && ((size_t)B * tpl > 1024 || (size_t)(B + 1) * L * esz > kLdsBudget)) B /= 2;
         int cp = 1 << ilog2(cols < 1 ? 1 : cols);
         if (cp < B) B = cp;
     }
@@ -212,7 +215,7 @@ void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int group
     p.tiles_per_group = (cols + B - 1) / B;
     p.grid = (unsigned)((long long)p.tiles_per_group * groups);
     p.block = (unsigned)(B * tpl);
-    p.shmem = (size_t)B * L * esz;
+    p.shmem = ((size_t)B * L + L) * esz; // tile + the staged twiddle table
 }
 
 // ----------------------------------------------------------------- launch
@@ -383,7 +386,7 @@ static void choose_strided(const Plan& plan, int L, int* vidx, int* B)
     for (int b = 256 / esz; b >= 1; b /= 2)
         for (int v : cands) {
             const int tpl = variant_tpl(plan.prec, v);
-            if ((long long)tpl * b <= 1024 && (size_t)b * L * esz <= 128 * 1024) {
+            if ((long long)tpl * b <= 1024 && (size_t)(b + 1) * L * esz <= 136 * 1024) {
                 *vidx = v;
                 *B = b;
                 return;
@@ -450,6 +453,86 @@ static bool want_transposed(const Plan& plan, int nc)
     return xstride >= (size_t)256 * 1024;
 }
 
+// Lines [line0, line0 + nlines) of a line pass as a pass of their own.
+// Offsets are in bytes; one line-map unit is one complex element (or one pair
+// of reals on the real side), i.e. `unit` bytes.
+static Pass line_chunk(const Pass& p, long long line0, long long nlines, size_t unit)
+{
+    Pass q = p;
+    q.nlines = nlines;
+    q.grid = (unsigned)((nlines + q.lines_per_wg - 1) / q.lines_per_wg);
+    if (p.ni >= p.nlines) { // contiguous line order: line l at l * s_i
+        q.ni = (int)nlines;
+        q.off_in = p.off_in + (long long)(line0 * p.is_i * (long long)unit);
+        q.off_out = p.off_out + (long long)(line0 * p.os_i * (long long)unit);
+    } else { // whole outer rows: line0 and nlines are multiples of ni
+        const long long lo = line0 / p.ni;
+        q.off_in = p.off_in + (long long)(lo * p.is_o * (long long)unit);
+        q.off_out = p.off_out + (long long)(lo * p.os_o * (long long)unit);
+    }
+    return q;
+}
+
+static Pass group_chunk(const Pass& p, int g0, int ng, size_t esz)
+{
+    Pass q = p;
+    q.groups = ng;
+    q.grid = (unsigned)((long long)q.tiles_per_group * ng);
+    q.off_in = p.off_in + (long long)g0 * p.gs_in * (long long)esz;
+    q.off_out = p.off_out + (long long)g0 * p.gs_out * (long long)esz;
+    return q;
+}
+
+// The transposed strategy's forward is z (lines of x-planes), y (tiles of
+// x-planes, writing W[k1][x][k2]), x; the y-tiles of plane x only need that
+// plane's z-lines.  Running z and y chunk by chunk, with chunks of about
+// 128 MiB, lets each y-chunk read what its z-chunk just wrote while it still
+// sits in the 256 MB Infinity Cache.  The inverse is chunked the same way
+// over k1-planes: x^-1 (tiles of k1-planes of W), then z^-1 of those planes.
+// MIFFT_CHUNK_MIB overrides the chunk size (0: no chunking).
+void apply_chunking(Plan& plan)
+{
+    const bool real = plan.kind == MIFFT_R2C;
+    const int nc = real ? plan.n2 / 2 + 1 : plan.n2;
+    const size_t plane_bytes = (size_t)plan.n1 * nc * plan.esz;
+    // opt-in: on the MI355X boxes measured so far the chunked order was slower
+    size_t target = 0;
+    if (const char* e = getenv("MIFFT_CHUNK_MIB")) target = (size_t)atol(e) << 20;
+    if (target == 0) return;
+    // balanced chunks of about `target` bytes; a single chunk is no pipeline
+    const int k = (int)std::max<size_t>(1, ((size_t)plan.n0 * plane_bytes + target - 1) / target);
+    if (k < 2) return;
+    const int C = (plan.n0 + k - 1) / k;
+    // forward: [z, y, x] with z over lines (x outer, y inner), y over x-groups
+    if (plan.fwd.size() == 3) {
+        const Pass z = plan.fwd[0], y = plan.fwd[1], x = plan.fwd[2];
+        std::vector<Pass> f;
+        for (int g0 = 0; g0 < plan.n0; g0 += C) {
+            const int ng = std::min(C, plan.n0 - g0);
+            f.push_back(line_chunk(z, (long long)g0 * plan.n1, (long long)ng * plan.n1, plan.esz));
+            f.push_back(group_chunk(y, g0, ng, plan.esz));
+        }
+        f.push_back(x);
+        plan.fwd = f;
+    }
+    // inverse: [y^-1, x^-1, z^-1]; x^-1 over k1-groups of W, z^-1 over lines (k1 outer)
+    if (plan.inv.size() == 3) {
+        const Pass y = plan.inv[0], x = plan.inv[1], z = plan.inv[2];
+        const size_t wplane = (size_t)plan.n0 * nc * plan.esz; // one k1-plane of W
+        const int kz = (int)std::max<size_t>(1, ((size_t)plan.n1 * wplane + target - 1) / target);
+        const int Cz = (plan.n1 + kz - 1) / kz;
+        std::vector<Pass> v;
+        v.push_back(y);
+        for (int g0 = 0; g0 < plan.n1; g0 += Cz) {
+            const int ng = std::min(Cz, plan.n1 - g0);
+            v.push_back(group_chunk(x, g0, ng, plan.esz));
+            v.push_back(line_chunk(z, (long long)g0 * plan.n0, (long long)ng * plan.n0, plan.esz));
+        }
+        plan.inv = v;
+    }
+    plan.chunks = (plan.n0 + C - 1) / C;
+}
+
 int build_plan(Plan& plan, unsigned /*flags*/)
 {
     const bool real = plan.kind == MIFFT_R2C;
@@ -470,11 +553,13 @@ int build_plan(Plan& plan, unsigned /*flags*/)
     if (real) {
         Pass z;
         if ((rc = make_real_z(plan, z, P_R2C))) return rc;
+        z.tag = 0;
         plan.fwd.push_back(z);
     } else if (has_z) {
         Pass z;
         if ((rc = make_contig(plan, z, n2, (long long)n0 * n1, vz))) return rc;
         z.sgn = +1;
+        z.tag = 0;
         plan.fwd.push_back(z);
     }
     if (n1 > 1) {
@@ -486,6 +571,7 @@ int build_plan(Plan& plan, unsigned /*flags*/)
             y.gs_out = nc;
         }
         y.sgn = +1;
+        y.tag = 1;
         plan.fwd.push_back(y);
     }
     if (n0 > 1) {
@@ -499,6 +585,7 @@ int build_plan(Plan& plan, unsigned /*flags*/)
             if ((rc = make_strided(plan, x, n0, (int)plane, 1, plane, 0, vx, 0))) return rc;
         }
         x.sgn = +1;
+        x.tag = 2;
         plan.fwd.push_back(x);
     }
     if (plan.fwd.empty()) { // 1 x 1 x 1 C2C: the identity
@@ -538,12 +625,14 @@ int build_plan(Plan& plan, unsigned /*flags*/)
         y.es_out = (long long)n0 * nc;
         y.gs_out = nc;
         y.sgn = -1;
+        y.tag = 1;
         y.src = B_IN;
         y.dst = B_WS;
         plan.inv.push_back(y);
         Pass x;
         if ((rc = make_strided(plan, x, n0, nc, n1, nc, (long long)n0 * nc, vx, 0))) return rc;
         x.sgn = -1;
+        x.tag = 2;
         x.src = x.dst = B_WS;
         if (!has_z) { // no z-pass to undo the transposition: x^-1 writes the standard layout
             x.es_out = plane;
@@ -553,16 +642,19 @@ int build_plan(Plan& plan, unsigned /*flags*/)
         plan.inv.push_back(x);
         if (has_z) {
             Pass z;
+            // lines in the order of W (k1 outer, x inner): line (y, x) of W
+            // is line (x, y) of the output, so a range of k1 planes is a
+            // contiguous range of lines
             if (real) {
                 if ((rc = make_real_z(plan, z, P_C2R))) return rc;
-                // line (x, y) of the output is line (y, x) of W
-                set_line_map(z, n1, (long long)nc, (long long)n0 * nc, (long long)n1 * (n2 / 2),
-                             (long long)(n2 / 2));
+                set_line_map(z, n0, (long long)n0 * nc, (long long)nc, (long long)(n2 / 2),
+                             (long long)n1 * (n2 / 2));
             } else {
                 if ((rc = make_contig(plan, z, n2, (long long)n0 * n1, vz))) return rc;
-                set_line_map(z, n1, (long long)n2, (long long)n0 * n2, (long long)n1 * n2, (long long)n2);
+                set_line_map(z, n0, (long long)n0 * n2, (long long)n2, (long long)n2, (long long)n1 * n2);
                 z.sgn = -1;
             }
+            z.tag = 0;
             z.src = B_WS;
             z.dst = B_OUT;
             plan.inv.push_back(z);
@@ -572,22 +664,26 @@ int build_plan(Plan& plan, unsigned /*flags*/)
             Pass x;
             if ((rc = make_strided(plan, x, n0, (int)plane, 1, plane, 0, vx, 0))) return rc;
             x.sgn = -1;
+            x.tag = 2;
             plan.inv.push_back(x);
         }
         if (n1 > 1) {
             Pass y;
             if ((rc = make_strided(plan, y, n1, nc, n0, nc, plane, vy, 0))) return rc;
             y.sgn = -1;
+            y.tag = 1;
             plan.inv.push_back(y);
         }
         if (real) {
             Pass z;
             if ((rc = make_real_z(plan, z, P_C2R))) return rc;
+            z.tag = 0;
             plan.inv.push_back(z);
         } else if (has_z) {
             Pass z;
             if ((rc = make_contig(plan, z, n2, (long long)n0 * n1, vz))) return rc;
             z.sgn = -1;
+            z.tag = 0;
             plan.inv.push_back(z);
         }
         if (plan.inv.empty()) {
@@ -613,6 +709,7 @@ int build_plan(Plan& plan, unsigned /*flags*/)
             v.back().dst = B_OUT;
         }
     }
+    if (T && has_z) apply_chunking(plan);
     bool inv_uses_ws = false, fwd_uses_ws = false;
     for (const Pass& q : plan.inv) inv_uses_ws |= (q.src == B_WS || q.dst == B_WS);
     for (const Pass& q : plan.fwd) fwd_uses_ws |= (q.src == B_WS || q.dst == B_WS);
@@ -706,6 +803,9 @@ int build_pencil(Plan& plan, unsigned /*flags*/)
     plan.py_split.src = B_RECV;
     plan.py_split.dst = B_OUT;
     plan.pz.sgn = plan.pz_pack.sgn = plan.py.sgn = plan.py_split.sgn = +1;
+    plan.pz.tag = plan.pz_pack.tag = 0;
+    plan.py.tag = plan.py_split.tag = 1;
+    plan.pk.tag = plan.upk.tag = 3;
     return MIFFT_OK;
 }
 

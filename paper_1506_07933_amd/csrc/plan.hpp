@@ -52,6 +52,9 @@ struct Pass {
     int n0 = 0, n1 = 0, n2c = 0, p1 = 0, M = 0;
     size_t bytes = 0;
     double scale = 1.0;
+    // byte offsets added to the resolved source / destination (chunked passes)
+    long long off_in = 0, off_out = 0;
+    int tag = 0; // 0 z, 1 y, 2 x, 3 other: for per-axis timing summaries
     // launch geometry
     unsigned grid = 0, block = 0;
     size_t shmem = 0;
@@ -71,6 +74,7 @@ public:
     // workspace so that the x-pass reads with a small stride (see plan.hip).
     bool transposed = false;
     bool plan_only = false; // no device resources: describe only
+    int chunks = 1;         // z/y (forward) and x/z (inverse) interleaved in this many chunks
     bool pencil = false;
     int p0 = 1, p1 = 1;
     int device = 0;
@@ -119,6 +123,7 @@ int get_twiddles(Plan& plan, int L, void** out);
 
 int build_plan(Plan& plan, unsigned flags);
 void rebuild_poisson(Plan& plan); // re-derive the Poisson pass list from fwd / inv
+void apply_chunking(Plan& plan);  // interleave z/y (x^-1/z^-1) over plane chunks
 int build_pencil(Plan& plan, unsigned flags);
 
 } // namespace mifft

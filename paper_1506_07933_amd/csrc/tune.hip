@@ -105,7 +105,7 @@ static bool apply_choice(const Plan& plan, Pass& p, int vidx, int shape)
     const size_t esz = plan.esz;
     if (p.kind == P_STRIDED) {
         const int B = shape;
-        if ((long long)B * tpl > 1024 || (size_t)B * p.L * esz > 160 * 1024) return false;
+        if ((long long)B * tpl > 1024 || (size_t)(B + 1) * p.L * esz > 160 * 1024) return false;
         int lg = 0;
         while ((1 << lg) < B) ++lg;
         p.vidx = vidx;
@@ -114,18 +114,18 @@ static bool apply_choice(const Plan& plan, Pass& p, int vidx, int shape)
         p.tiles_per_group = (p.cols + B - 1) / B;
         p.grid = (unsigned)((long long)p.tiles_per_group * p.groups);
         p.block = (unsigned)(B * tpl);
-        p.shmem = (size_t)B * p.L * esz;
+        p.shmem = ((size_t)B * p.L + p.L) * esz;
         return true;
     }
     const int lpw = shape;
-    if ((long long)lpw * tpl > 1024 || (size_t)lpw * lds_len_of(p) * esz > 160 * 1024) return false;
+    if ((long long)lpw * tpl > 1024 || ((size_t)lpw * lds_len_of(p) + p.L) * esz > 160 * 1024) return false;
     const int ni = p.ni;
     const long long is_o = p.is_o, is_i = p.is_i, os_o = p.os_o, os_i = p.os_i;
     p.vidx = vidx;
     p.lines_per_wg = lpw;
     p.grid = (unsigned)((p.nlines + lpw - 1) / lpw);
     p.block = (unsigned)(lpw * tpl);
-    p.shmem = (size_t)lpw * lds_len_of(p) * esz;
+    p.shmem = ((size_t)lpw * lds_len_of(p) + p.L) * esz;
     set_line_map(p, ni, is_o, is_i, os_o, os_i);
     return true;
 }

@@ -34,7 +34,10 @@ def _csv(d: str, suffix: str):
 
 
 def _fft_dispatches(rows, skip=("twiddles",)):
-    rows = [r for r in rows if not any(s in r["Kernel_Name"] for s in skip)]
+    """The transform's own dispatches (library kernels other than the twiddle
+    generator), in launch order."""
+    rows = [r for r in rows if "mifft::k_" in r["Kernel_Name"]
+            and not any(s in r["Kernel_Name"] for s in skip)]
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     return rows
 

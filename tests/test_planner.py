@@ -51,28 +51,55 @@ def test_launch_shapes_cover_and_fit(shape, prec, kind):
         assert 1 <= block <= 1024
         assert lds <= 160 * 1024
         if p["kind"] in ("contig", "r2c_z", "c2r_z"):
-            lines, lpw, tpl = ints(p, "lines", "lpw", "tpl")
+            lines, lpw, tpl, L = ints(p, "lines", "lpw", "tpl", "L")
             assert block == lpw * tpl
             assert grid * lpw >= lines > (grid - 1) * lpw
+            # per-line tiles (padded; real kernels hold L + 1 points) + the twiddle table
+            n = L if p["kind"] == "contig" else L + 1
+            assert lds == (lpw * (n + (n >> 3) + 1) + L) * esz
         elif p["kind"] == "strided":
             B, cols, groups, tpl, L = ints(p, "B", "cols", "groups", "tpl", "L")
             assert B & (B - 1) == 0 and block == B * tpl
             tiles = -(-cols // B)
             assert grid == tiles * groups
-            assert lds == B * L * esz
+            assert lds == (B * L + L) * esz  # column tile + the twiddle table
 
 
-def test_512_cube_uses_transposed_intermediate():
+def test_512_cube_default_schedule_is_unchunked():
+    passes, ws, _ = plan_only(512, 512, 512)
+    assert ws == 512 ** 3 * 8
+    assert [p["axis"] for p in passes if p["dir"] == "forward"] == ["z", "y", "x"]
+    assert [p["axis"] for p in passes if p["dir"] == "inverse"] == ["y", "x", "z"]
+
+
+def test_512_cube_chunked_transposed_intermediate(monkeypatch):
+    monkeypatch.setenv("MIFFT_CHUNK_MIB", "128")
     passes, ws, _ = plan_only(512, 512, 512)
     assert ws == 512 ** 3 * 8
     fwd = [p for p in passes if p["dir"] == "forward"]
-    assert [p["kind"] for p in fwd] == ["contig", "strided", "strided"]
-    y, x = fwd[1], fwd[2]
-    # y reads with stride n2 and writes W[k1][x][k2] (stride n0 n2)
-    assert y["es"] == "512/262144" and y["gs"] == "262144/512"
+    # z and y interleaved over x-plane chunks, then x
+    assert [p["axis"] for p in fwd] == ["z", "y"] * (len(fwd) // 2) + ["x"]
+    zs, ys, x = fwd[0:-1:2], fwd[1:-1:2], fwd[-1]
+    assert sum(int(p["lines"]) for p in zs) == 512 * 512
+    assert sum(int(p["groups"]) for p in ys) == 512
+    # chunk k starts where chunk k-1 ended (byte offsets)
+    line_bytes = 512 * 8
+    off = 0
+    for z in zs:
+        assert z["off"] == "%d/%d" % (off, off)
+        off += int(z["lines"]) * line_bytes
+    g = 0
+    for y in ys:
+        # y reads x-planes (stride n1 n2) and writes W[k1][x][k2] (x stride n2)
+        assert y["es"] == "512/262144" and y["gs"] == "262144/512"
+        assert y["off"] == "%d/%d" % (g * 262144 * 8, g * 512 * 8)
+        g += int(y["groups"])
     # x reads W with stride n2 and writes the standard layout (stride n1 n2)
-    assert x["es"] == "512/262144" and x["gs"] == "262144/512"
+    assert x["es"] == "512/262144" and x["gs"] == "262144/512" and x["groups"] == "512"
     assert x["B"] == "32" and x["tpl"] == "32"
+    inv = [p for p in passes if p["dir"] == "inverse"]
+    assert [p["axis"] for p in inv] == ["y"] + ["x", "z"] * ((len(inv) - 1) // 2)
+    assert sum(int(p["lines"]) for p in inv if p["axis"] == "z") == 512 * 512
 
 
 def test_small_grid_keeps_standard_layout():
@@ -105,5 +132,5 @@ def test_pencil_plan_only_describes_fused_stages():
                                         MIFFT_PLAN_ONLY) == 0
     text = plan_describe(h.value)
     plan_destroy(h.value)
-    assert "pencil_z_pack kind=contig_pack L=1024" in text
-    assert "pencil_unpack_y kind=strided_unpack L=1024" in text
+    assert "pencil_z_pack kind=contig_pack axis=z L=1024" in text
+    assert "pencil_unpack_y kind=strided_unpack axis=y L=1024" in text
