@@ -115,6 +115,11 @@ int mifft_plan_create(mifft_plan* out, int n0, int n1, int n2, int kind, int pre
     p->kind = kind;
     p->prec = prec;
     p->device = dev;
+    if (!plan_only) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p->cus = cus;
+    }
     p->esz = prec == MIFFT_FP64 ? 16 : 8;
     if ((rc = build_plan(*p, flags))) {
         delete p;
@@ -179,6 +184,11 @@ int mifft_plan_create_pencil(mifft_plan* out, int n0, int n1, int n2, int p0, in
     p->kind = kind;
     p->prec = prec;
     p->device = dev;
+    if (!plan_only) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p->cus = cus;
+    }
     p->esz = prec == MIFFT_FP64 ? 16 : 8;
     if ((rc = build_pencil(*p, flags))) {
         delete p;
@@ -421,12 +431,14 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
         char line[320];
         int pol = q.vidx >= 0 ? variant_policy(plan->prec, q.vidx) : -1;
         int tpl = q.vidx >= 0 ? variant_tpl(plan->prec, q.vidx) : 0;
+        const bool strided = q.kind == mifft::P_STRIDED || q.kind == mifft::P_STRIDED_SPLIT;
+        int pf = strided && q.vidx >= 0 ? variant_prefetch(plan->prec, q.vidx) : 0;
         snprintf(line, sizeof(line),
                  "%s kind=%s axis=%c L=%d policy=%d tpl=%d sgn=%d lines=%lld lpw=%d B=%d cols=%d groups=%d "
-                 "es=%lld/%lld gs=%lld/%lld off=%lld/%lld grid=%u block=%u lds=%zu\n",
+                 "es=%lld/%lld gs=%lld/%lld off=%lld/%lld grid=%u block=%u lds=%zu pf=%d\n",
                  tag, kn[q.kind], "zyx-"[q.tag < 3 ? q.tag : 3], q.L, pol, tpl, q.sgn, q.nlines, q.lines_per_wg,
                  q.B, q.cols, q.groups, q.es_in, q.es_out, q.gs_in, q.gs_out, q.off_in, q.off_out, q.grid,
-                 q.block, q.shmem);
+                 q.block, q.shmem, pf);
         s += line;
     };
     if (plan->pencil) {

@@ -16,10 +16,17 @@
 // stage code serves the contiguous-axis, strided-axis, R2C, C2R and fused
 // pack / unpack kernels.  Inverse transforms use conj(F(conj(x))), so only
 // forward butterflies and forward twiddles exist.
+//
+// A context that sets kPrefetch holds the first stage's inputs in registers
+// (loaded ahead of time) and is asked, right after the first stage has
+// consumed them, to load the inputs of its next tile into the same
+// registers, so those loads are in flight while the rest of the current
+// tile is transformed and stored.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace mifft {
 
@@ -210,6 +217,33 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t k, FastDiv f)
 
 // ---------------------------------------------------------------- stages
 
+// Contexts that declare kPrefetch = true supply first_get(slot) and
+// prefetch_next<L, TPL, R>() (see FirstStageShape).
+template <typename C, typename = void> struct ctx_prefetches : std::false_type {};
+template <typename C>
+struct ctx_prefetches<C, std::void_t<decltype(C::kPrefetch)>> : std::integral_constant<bool, C::kPrefetch> {};
+
+// The first stage's input positions: thread t reads, for its butterflies
+// i = 0 .. NB-1 (j = t + i TPL < L/R) and r = 0 .. R-1, element j + r L/R
+// into register slot i R + r.  each() visits (slot, element) in that order.
+template <int L, int TPL, int R> struct FirstStageShape {
+    static constexpr int NBF = L / R;
+    static constexpr int NB = (NBF + TPL - 1) / TPL;
+    static constexpr bool EXACT = (NBF % TPL) == 0;
+    static constexpr int SLOTS = NB * R;
+    template <typename F> __device__ __forceinline__ static void each(int t, F&& f)
+    {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * TPL;
+            if (EXACT || j < NBF) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) f(i * R + r, j + r * NBF);
+            }
+        }
+    }
+};
+
 template <typename T, int L, int TPL, int Ns, bool FIRST, typename Ctx, int R, int... Rest>
 struct Stage {
     __device__ __forceinline__ static void run(Ctx& c)
@@ -219,6 +253,7 @@ struct Stage {
         constexpr int NB = (NBF + TPL - 1) / TPL; // butterflies per thread
         constexpr bool EXACT = (NBF % TPL) == 0;
         constexpr bool LAST = sizeof...(Rest) == 0;
+        constexpr bool PF = FIRST && ctx_prefetches<Ctx>::value;
         V v[NB][R];
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -226,13 +261,16 @@ struct Stage {
             if (EXACT || j < NBF) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    if constexpr (FIRST)
+                    if constexpr (PF)
+                        v[i][r] = c.first_get(i * R + r);
+                    else if constexpr (FIRST)
                         v[i][r] = c.gload(j + r * NBF);
                     else
                         v[i][r] = c.lds_get(j + r * NBF);
                 }
             }
         }
+        if constexpr (PF) c.template prefetch_next<L, TPL, R>();
         if constexpr (!FIRST || Ctx::kSyncAfterFirstRead) c.sync();
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -263,6 +301,13 @@ struct Stage {
 };
 
 template <int... R> struct RadixList {};
+template <typename RLt> struct FirstRadix;
+template <int R0, int... Rest> struct FirstRadix<RadixList<R0, Rest...>> {
+    static constexpr int value = R0;
+};
+template <> struct FirstRadix<RadixList<>> {
+    static constexpr int value = 1; // length 1: no stage
+};
 
 template <typename T, int L, int TPL, typename Ctx, typename RL> struct LineFFT;
 template <typename T, int L, int TPL, typename Ctx, int... R>

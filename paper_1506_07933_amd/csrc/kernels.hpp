@@ -65,9 +65,14 @@ template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
     }
 };
 
-template <typename T, bool IN_SPLIT> struct StridedCtx {
+// A strided workgroup transforms one column tile after another (tile,
+// tile + grid, ...).  With PF the first stage's inputs of the next tile are
+// loaded into registers while the current tile finishes (kPrefetch); PF is
+// used where those registers fit next to the transform's own.
+template <typename T, bool IN_SPLIT, int SLOTS, bool PF> struct StridedCtx {
     using V = cx<T>;
     static constexpr bool kSyncAfterFirstRead = false;
+    static constexpr bool kPrefetch = PF;
     const V* __restrict__ in;
     V* __restrict__ out;
     V* lds; // column c of the tile: element idx at lds[idx * B]
@@ -79,20 +84,51 @@ template <typename T, bool IN_SPLIT> struct StridedCtx {
     long long es_in, es_out; // element strides
     FastDiv split;           // IN_SPLIT: y = q * split.d + rem, address q * s_hi + rem * es_in
     long long s_hi;
+    V pre[SLOTS];            // first-stage inputs of the current tile
+    const V* nin;            // next tile: input column, and whether it is a real column
+    bool nvalid;
+    bool has_next;
 
-    __device__ __forceinline__ V gload(int idx) const
+    __device__ __forceinline__ V raw_load(const V* __restrict__ base, bool ok, int idx) const
     {
         V v{T(0), T(0)};
-        if (valid) {
+        if (ok) {
             if constexpr (IN_SPLIT) {
                 uint32_t q = fdiv((uint32_t)idx, split);
-                v = in[(long long)q * s_hi + (long long)(idx - (int)(q * split.d)) * es_in];
+                v = base[(long long)q * s_hi + (long long)(idx - (int)(q * split.d)) * es_in];
             } else {
-                v = in[(long long)idx * es_in];
+                v = base[(long long)idx * es_in];
             }
         }
+        return v;
+    }
+    __device__ __forceinline__ V gload(int idx) const
+    {
+        V v = raw_load(in, valid, idx);
         v.y *= sgn;
         return v;
+    }
+    template <int L, int TPL, int R> __device__ __forceinline__ void load_first(const V* base, bool ok)
+    {
+        using S = FirstStageShape<L, TPL, R>;
+#pragma unroll
+        for (int i = 0; i < S::NB; ++i) {
+            const int j = t + i * TPL;
+            if (S::EXACT || j < S::NBF) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pre[i * R + r] = raw_load(base, ok, j + r * S::NBF);
+            }
+        }
+    }
+    __device__ __forceinline__ V first_get(int slot) const
+    {
+        V v = pre[slot];
+        v.y *= sgn;
+        return v;
+    }
+    template <int L, int TPL, int R> __device__ __forceinline__ void prefetch_next()
+    {
+        if (has_next) load_first<L, TPL, R>(nin, nvalid);
     }
     __device__ __forceinline__ V lds_get(int idx) const { return lds[idx * B]; }
     __device__ __forceinline__ void lds_put(int idx, V v) { lds[idx * B] = v; }
@@ -253,6 +289,7 @@ template <typename T> struct StridedArgs {
     int log2B;
     int cols;            // columns per group
     int tiles_per_group; // ceil(cols / B)
+    int groups;
     long long gs_in, gs_out; // group strides
     long long es_in, es_out; // element strides
     T sgn;
@@ -260,33 +297,74 @@ template <typename T> struct StridedArgs {
     long long s_hi;
 };
 
+// Whether the strided kernel of (T, L, policy, TPL) prefetches the next
+// tile: only where the prefetched data (first-stage elements per thread)
+// fits in 32 VGPRs next to the transform's own registers without spilling
+// at 1024 threads per workgroup (FP32; FP64 variants run the plain tile loop).
+template <typename T, int L, int P, int TPL> constexpr bool strided_prefetches()
+{
+    using S = FirstStageShape<L, TPL, FirstRadix<typename RL<L, P>::type>::value>;
+    return sizeof(T) == 4 && L > 1 && S::SLOTS * sizeof(cx<T>) <= 128;
+}
+
+// Tiles are numbered group-major (tile = group * tiles_per_group + column
+// block); workgroup b takes tiles b, b + grid, b + 2 grid, ... (the grid may
+// be smaller than the number of tiles, never larger).
 template <typename T, int L, int P, int TPL, bool IN_SPLIT>
 __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
 {
     using V = cx<T>;
+    using RLt = typename RL<L, P>::type;
+    constexpr int R0 = FirstRadix<RLt>::value;
+    using Shape = FirstStageShape<L, TPL, R0>;
+    constexpr bool PF = strided_prefetches<T, L, P, TPL>();
+    const int ntiles = a.tiles_per_group * a.groups;
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return; // uniform: the whole workgroup leaves
     extern __shared__ unsigned char smem_raw[];
     V* smem = reinterpret_cast<V*>(smem_raw);
     const int tid = threadIdx.x;
     const int cc = tid & (a.B - 1);
-    const int t = tid >> a.log2B;
-    const int tile = blockIdx.x;
-    const int g = tile / a.tiles_per_group;
-    const int cb = tile - g * a.tiles_per_group;
-    const int col = cb * a.B + cc;
-    StridedCtx<T, IN_SPLIT> c;
-    c.valid = col < a.cols;
-    c.in = a.in + (long long)g * a.gs_in + col;
-    c.out = a.out + (long long)g * a.gs_out + col;
+    StridedCtx<T, IN_SPLIT, Shape::SLOTS, PF> c;
     c.lds = smem + cc;
     c.twd = stage_twiddles<T>(a.tw, L, smem + a.B * L);
-    c.t = t;
+    c.t = tid >> a.log2B;
     c.B = a.B;
     c.sgn = a.sgn;
     c.es_in = a.es_in;
     c.es_out = a.es_out;
     c.split = a.split;
     c.s_hi = a.s_hi;
-    LineFFT<T, L, TPL, decltype(c), typename RL<L, P>::type>::run(c);
+    // column of this thread in a tile; false for the padding columns of a ragged tile
+    auto locate = [&](int tl, long long& in_off, long long& out_off) -> bool {
+        const int g = tl / a.tiles_per_group;
+        const int col = (tl - g * a.tiles_per_group) * a.B + cc;
+        in_off = (long long)g * a.gs_in + col;
+        out_off = (long long)g * a.gs_out + col;
+        return col < a.cols;
+    };
+    long long io = 0, oo = 0;
+    c.valid = locate(tile, io, oo);
+    c.in = a.in + io;
+    c.out = a.out + oo;
+    if constexpr (PF) c.template load_first<L, TPL, R0>(c.in, c.valid);
+    for (;;) {
+        // Hide the strides' loop invariance: hoisting the per-element address
+        // products out of the tile loop would hold them all in registers.
+        asm volatile("" : "+v"(c.es_in), "+v"(c.es_out), "+v"(c.B), "+v"(c.t));
+        const int next = tile + (int)gridDim.x;
+        c.has_next = next < ntiles;
+        long long nio = 0, noo = 0;
+        c.nvalid = c.has_next ? locate(next, nio, noo) : false;
+        c.nin = a.in + nio;
+        LineFFT<T, L, TPL, decltype(c), RLt>::run(c);
+        if (!c.has_next) break;
+        __syncthreads(); // the next tile's first stage overwrites the LDS tile
+        tile = next;
+        c.valid = c.nvalid;
+        c.in = c.nin;
+        c.out = a.out + noo;
+    }
 }
 
 // Lines are mapped as in ContigArgs; offsets count complex elements of the

@@ -113,6 +113,10 @@ int variant_emul(int prec, int i)
 {
     return with_table(prec, [i](const auto& t) { return t[i].emul; });
 }
+int variant_prefetch(int prec, int i)
+{
+    return with_table(prec, [i](const auto& t) { return t[i].prefetch; });
+}
 
 int find_variant(int prec, int L, int policy, int emul)
 {
@@ -235,6 +239,33 @@ static void ensure_lds(const void* fn, size_t bytes)
         cur = bytes;
 }
 
+void strided_grid(const Plan& plan, Pass& p)
+{
+    const long long ntiles = (long long)p.tiles_per_group * p.groups;
+    p.grid = (unsigned)ntiles;
+    if (const char* e = getenv("MIFFT_STRIDED_PERSIST"))
+        if (atoi(e) == 0) return;
+    if (p.vidx < 0 || !variant_prefetch(plan.prec, p.vidx)) return;
+    int per_cu = 0;
+    if (!plan.plan_only) {
+        const void* fn = with_table(plan.prec, [&](const auto& t) {
+            return p.kind == P_STRIDED_SPLIT ? reinterpret_cast<const void*>(t[p.vidx].strided_split)
+                                             : reinterpret_cast<const void*>(t[p.vidx].strided);
+        });
+        ensure_lds(fn, p.shmem);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)p.block, p.shmem) != hipSuccess) {
+            (void)hipGetLastError();
+            per_cu = 0;
+        }
+    }
+    if (per_cu <= 0) { // estimate from LDS and threads (no device)
+        per_cu = (int)std::min<size_t>((size_t)160 * 1024 / std::max<size_t>(p.shmem, 1), 2048 / p.block);
+        per_cu = std::max(per_cu, 1);
+    }
+    const long long cap = (long long)plan.cus * per_cu;
+    if (ntiles > cap) p.grid = (unsigned)cap;
+}
+
 template <typename T>
 static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStream_t s)
 {
@@ -272,6 +303,7 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.log2B = p.log2B;
         a.cols = p.cols;
         a.tiles_per_group = p.tiles_per_group;
+        a.groups = p.groups;
         a.gs_in = p.gs_in;
         a.gs_out = p.gs_out;
         a.es_in = p.es_in;
@@ -405,6 +437,7 @@ static int make_strided(Plan& plan, Pass& p, int L, int cols, int groups, long l
     int rc = get_twiddles(plan, L, (void**)&p.tw);
     if (rc) return rc;
     set_strided_geometry(p, plan.prec, variant_tpl(plan.prec, vidx), L, cols, groups, forceB);
+    strided_grid(plan, p);
     p.es_in = p.es_out = es;
     p.gs_in = p.gs_out = gs;
     return MIFFT_OK;
@@ -473,11 +506,11 @@ static Pass line_chunk(const Pass& p, long long line0, long long nlines, size_t 
     return q;
 }
 
-static Pass group_chunk(const Pass& p, int g0, int ng, size_t esz)
+static Pass group_chunk(const Plan& plan, const Pass& p, int g0, int ng, size_t esz)
 {
     Pass q = p;
     q.groups = ng;
-    q.grid = (unsigned)((long long)q.tiles_per_group * ng);
+    strided_grid(plan, q);
     q.off_in = p.off_in + (long long)g0 * p.gs_in * (long long)esz;
     q.off_out = p.off_out + (long long)g0 * p.gs_out * (long long)esz;
     return q;
@@ -510,7 +543,7 @@ void apply_chunking(Plan& plan)
         for (int g0 = 0; g0 < plan.n0; g0 += C) {
             const int ng = std::min(C, plan.n0 - g0);
             f.push_back(line_chunk(z, (long long)g0 * plan.n1, (long long)ng * plan.n1, plan.esz));
-            f.push_back(group_chunk(y, g0, ng, plan.esz));
+            f.push_back(group_chunk(plan, y, g0, ng, plan.esz));
         }
         f.push_back(x);
         plan.fwd = f;
@@ -525,7 +558,7 @@ void apply_chunking(Plan& plan)
         v.push_back(y);
         for (int g0 = 0; g0 < plan.n1; g0 += Cz) {
             const int ng = std::min(Cz, plan.n1 - g0);
-            v.push_back(group_chunk(x, g0, ng, plan.esz));
+            v.push_back(group_chunk(plan, x, g0, ng, plan.esz));
             v.push_back(line_chunk(z, (long long)g0 * plan.n0, (long long)ng * plan.n0, plan.esz));
         }
         plan.inv = v;

@@ -78,6 +78,7 @@ public:
     bool pencil = false;
     int p0 = 1, p1 = 1;
     int device = 0;
+    int cus = 256;  // compute units of the device (persistent grids)
     size_t esz = 8; // bytes per complex element
     std::vector<Pass> fwd, inv, poisson;
     // pencil stages
@@ -104,6 +105,7 @@ int variant_L(int prec, int idx);
 int variant_tpl(int prec, int idx);
 int variant_policy(int prec, int idx);
 int variant_emul(int prec, int idx);
+int variant_prefetch(int prec, int idx);
 int find_variant(int prec, int L, int policy, int emul);
 int default_variant(int prec, int L);
 
@@ -112,6 +114,10 @@ FastDiv make_fastdiv(uint32_t d);
 
 // Launch geometry heuristics.
 void set_contig_geometry(Pass& p, int prec, int tpl, int L, long long nlines, int lds_len);
+// Grid of a strided pass whose tile shape is set: one workgroup per tile, or,
+// for kernels that prefetch their next tile, at most as many workgroups as
+// the device holds at once (each then walks tiles with the grid's stride).
+void strided_grid(const Plan& plan, Pass& p);
 void set_line_map(Pass& p, int ni, long long is_o, long long is_i, long long os_o, long long os_i);
 void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int groups, int forceB);
 

@@ -16,6 +16,7 @@ template <typename T> struct Variant {
     int policy;
     int emul;
     int tpl;     // threads per line
+    int prefetch; // the strided kernel prefetches the next column tile
     int nstages;
     int radix[24];
     ContigFn<T> contig;

@@ -112,9 +112,9 @@ static bool apply_choice(const Plan& plan, Pass& p, int vidx, int shape)
         p.B = B;
         p.log2B = lg;
         p.tiles_per_group = (p.cols + B - 1) / B;
-        p.grid = (unsigned)((long long)p.tiles_per_group * p.groups);
         p.block = (unsigned)(B * tpl);
         p.shmem = ((size_t)B * p.L + p.L) * esz;
+        strided_grid(plan, p);
         return true;
     }
     const int lpw = shape;

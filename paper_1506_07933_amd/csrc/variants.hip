@@ -22,6 +22,7 @@ template <int L, int P, int E> constexpr Variant<MIFFT_REAL> make_variant()
     v.policy = P;
     v.emul = E;
     v.tpl = TPL;
+    v.prefetch = strided_prefetches<MIFFT_REAL, L, P, TPL>() ? 1 : 0;
     v.nstages = f.n;
     for (int i = 0; i < f.n; ++i) v.radix[i] = f.r[i];
     v.contig = &k_contig<MIFFT_REAL, L, P, TPL, false>;

@@ -61,7 +61,13 @@ def test_launch_shapes_cover_and_fit(shape, prec, kind):
             B, cols, groups, tpl, L = ints(p, "B", "cols", "groups", "tpl", "L")
             assert B & (B - 1) == 0 and block == B * tpl
             tiles = -(-cols // B)
-            assert grid == tiles * groups
+            if p["pf"] == "1":
+                # prefetching kernels walk the tiles with a grid of at most one
+                # resident wave of workgroups (256 CUs x workgroups per CU)
+                per_cu = max(1, min(160 * 1024 // lds, 2048 // block))
+                assert grid == min(tiles * groups, 256 * per_cu)
+            else:
+                assert grid == tiles * groups
             assert lds == (B * L + L) * esz  # column tile + the twiddle table
 
 
@@ -96,7 +102,7 @@ def test_512_cube_chunked_transposed_intermediate(monkeypatch):
         g += int(y["groups"])
     # x reads W with stride n2 and writes the standard layout (stride n1 n2)
     assert x["es"] == "512/262144" and x["gs"] == "262144/512" and x["groups"] == "512"
-    assert x["B"] == "32" and x["tpl"] == "32"
+    assert x["B"] == "32" and x["tpl"] == "32" and x["pf"] == "1"
     inv = [p for p in passes if p["dir"] == "inverse"]
     assert [p["axis"] for p in inv] == ["y"] + ["x", "z"] * ((len(inv) - 1) // 2)
     assert sum(int(p["lines"]) for p in inv if p["axis"] == "z") == 512 * 512
