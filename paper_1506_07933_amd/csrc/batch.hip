@@ -152,7 +152,7 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
         // ---- passes in queue order: all z, then all y, then all x
         std::vector<BatchPass>& P = b->passes;
         std::vector<int> last(count, -1); // index of each transform's latest pass
-        size_t max_wave_lds = 0;
+        size_t max_lds = 0; // dynamic LDS elements of the largest pass
         // data per queue item (MIFFT_BATCH_ITEM_KIB overrides the 64 KiB default)
         size_t item_bytes = 64 * 1024;
         if (const char* e = getenv("MIFFT_BATCH_ITEM_KIB")) {
@@ -160,7 +160,14 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
             if (v > 0 && v <= 64 * 1024) item_bytes = (size_t)v * 1024;
         }
         for (int stage = 0; stage < 3; ++stage) {
-            for (int t = 0; t < count; ++t) {
+            // Within a stage the passes are ordered by line length, so that the
+            // workgroups running at any moment mostly execute the same
+            // per-length code (one instruction-cache working set, not many).
+            std::vector<int> order(count);
+            for (int t = 0; t < count; ++t) order[t] = t;
+            auto len_of = [&](int t) { return dims[3 * t + (stage == 0 ? 2 : (stage == 1 ? 1 : 0))]; };
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return len_of(a) < len_of(b); });
+            for (int t : order) {
                 const int n0 = dims[3 * t], n1 = dims[3 * t + 1], n2 = dims[3 * t + 2];
                 const int L = stage == 0 ? n2 : (stage == 1 ? n1 : n0);
                 if (L == 1) continue;
@@ -171,7 +178,8 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
                 p.tpl = threads_per_line(L, 0, 1);
                 p.xform = t;
                 p.from_in = last[t] < 0 ? 1 : 0;
-                p.per_wave = 64 / p.tpl;
+                // z: lines per wavefront sub-tile; y / x: columns per workgroup tile
+                p.per_wave = stage == 0 ? 64 / p.tpl : batch_tile_cols(p.tpl);
                 if (stage == 0) {
                     p.units = (long long)n0 * n1;
                     p.subtiles = (int)((p.units + p.per_wave - 1) / p.per_wave);
@@ -190,10 +198,12 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
                     p.subtiles = p.subtiles_per_group;
                     p.units = p.cols;
                 }
-                // queue items of ~item_bytes of data, a multiple of the wavefronts per workgroup
+                // queue items of ~item_bytes of data; z items are a multiple of the
+                // wavefronts per workgroup (one sub-tile run per wavefront)
                 const size_t sub_bytes = (size_t)p.per_wave * L * esz;
-                int spi = (int)((item_bytes + sub_bytes * kBatchWaves - 1) / (sub_bytes * kBatchWaves)) * kBatchWaves;
-                spi = std::max(kBatchWaves, std::min(spi, ((p.subtiles + kBatchWaves - 1) / kBatchWaves) * kBatchWaves));
+                const int unit = stage == 0 ? kBatchWaves : 1;
+                int spi = (int)((item_bytes + sub_bytes * unit - 1) / (sub_bytes * unit)) * unit;
+                spi = std::max(unit, std::min(spi, ((p.subtiles + unit - 1) / unit) * unit));
                 p.sub_per_item = spi;
                 p.nitems = (p.subtiles + spi - 1) / spi;
                 p.stage = stage;
@@ -220,7 +230,7 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
                 p.tw = it->second;
                 last[t] = (int)P.size();
                 P.push_back(p);
-                max_wave_lds = std::max(max_wave_lds, (size_t)batch_wave_lds(L, p.tpl));
+                max_lds = std::max(max_lds, (size_t)batch_lds_elems(L, p.tpl, prec == MIFFT_FP32));
             }
         }
         int start = 0;
@@ -231,7 +241,7 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
         }
         b->total_items = start;
         b->ncounters = (int)P.size() + 2 + kBatchStages;
-        b->lds = max_wave_lds * esz * kBatchWaves;
+        b->lds = max_lds * esz;
         if (hipMalloc(&b->d_passes, sizeof(BatchPass) * P.size()) != hipSuccess ||
             hipMalloc(&b->d_counters, sizeof(int) * b->ncounters) != hipSuccess) {
             delete b;

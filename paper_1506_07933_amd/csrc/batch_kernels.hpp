@@ -26,10 +26,15 @@
 // leaves, publishing then.  Every wait is bounded as well: a wait that
 // exceeds its bound raises an abort flag that makes every workgroup leave.
 //
-// Inside an item each wavefront transforms its own lines (z) or its own
-// columns (y, x) with the Stockham engine, synchronising only within the
-// wavefront; lanes left over when the threads per line do not divide 64 work
-// on a private dummy line or column whose results are discarded.
+// Inside a z-item each wavefront transforms its own contiguous lines,
+// synchronising only within the wavefront.  A y- or x-item is a run of
+// column tiles that the whole workgroup transforms one after another: a
+// tile is as many adjacent columns as the workgroup holds lines of that
+// length (256 / threads per line), so each row of a tile is one contiguous
+// run of 64 bytes or more (narrow per-wavefront column tiles made the
+// strided passes several times slower).  Lanes left over when the threads
+// per line do not divide the wavefront or workgroup work on a private dummy
+// line or column whose results are discarded.
 #pragma once
 
 #include <stddef.h>
@@ -91,9 +96,13 @@ template <typename T> struct BatchArgs {
     cx<T>* out[kBatchMax];
 };
 
-// Dynamic LDS of the persistent kernel, named at file scope so that device
-// functions address it as LDS (not through generic pointers).
-extern __shared__ unsigned char mifft_batch_lds[];
+// Dynamic LDS of the persistent kernel.  The kernel hands its base to the
+// per-length functions as an LDS-address-space pointer: referenced from a
+// non-inlined function, the symbol itself would be located through a global
+// offset table, a memory load (and a full wait on all outstanding loads) at
+// every use.
+extern __shared__ __attribute__((aligned(16))) unsigned char mifft_batch_lds[];
+#define MIFFT_LDS __attribute__((address_space(3)))
 
 // Pointers read from memory are generic; the wave contexts hold them as
 // global (address space 1) pointers so the compiler emits global, not flat,
@@ -110,75 +119,140 @@ template <typename T> struct vec2_of;
 template <> struct vec2_of<float> { typedef float type __attribute__((ext_vector_type(2))); };
 template <> struct vec2_of<double> { typedef double type __attribute__((ext_vector_type(2))); };
 
-template <typename T> struct WaveContigCtx {
+// Wave-local context of one sub-tile: lines (KIND 0: element idx of a line
+// at idx) or columns (KIND 1: element idx at idx * es).  The first stage's
+// inputs are prefetched into registers (PF: the next sub-tile's are loaded
+// while the current one finishes), and the twiddles are read from the
+// wavefront's LDS copy (TWL) or from global memory.
+template <typename T, int KIND, int SLOTS, bool PF, bool TWL, bool WG = false> struct WaveCtx {
     using V = cx<T>;
     typedef typename vec2_of<T>::type N2;
     typedef MIFFT_GLOBAL N2 GN2;
     static constexpr bool kSyncAfterFirstRead = false;
+    static constexpr bool kPrefetch = PF;
+    typedef MIFFT_LDS N2 LN2;
     const GN2* in;
     GN2* out;
-    V* lds;
-    const GN2* twd;
+    LN2* lds;
+    const LN2* twl; // TWL: the twiddle copy in LDS
+    const GN2* twg; // otherwise: the twiddles in global memory
     int t;
+    int rs;         // KIND 1: LDS row stride (columns of the sub-tile + 1)
     bool valid;
-    __device__ __forceinline__ V gload(int idx) const
+    long long es;   // KIND 1: element stride
+    V pre[SLOTS > 0 ? SLOTS : 1];
+    const GN2* nin;
+    bool nvalid;
+    bool has_next;
+
+    __device__ __forceinline__ V raw(const GN2* base, bool ok, int idx) const
     {
-        N2 r = valid ? in[idx] : N2{T(0), T(0)};
+        N2 r = N2{T(0), T(0)};
+        if (ok) r = KIND == 0 ? base[idx] : base[(long long)idx * es];
         return V{r.x, r.y};
     }
-    __device__ __forceinline__ V lds_get(int idx) const { return lds[lds_pad(idx)]; }
-    __device__ __forceinline__ void lds_put(int idx, V v) { lds[lds_pad(idx)] = v; }
+    __device__ __forceinline__ V gload(int idx) const { return raw(in, valid, idx); }
+    template <int L, int TPL, int R> __device__ __forceinline__ void load_first(const GN2* base, bool ok)
+    {
+        using S = FirstStageShape<L, TPL, R>;
+#pragma unroll
+        for (int i = 0; i < S::NB; ++i) {
+            const int j = t + i * TPL;
+            if (S::EXACT || j < S::NBF) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pre[i * R + r] = raw(base, ok, j + r * S::NBF);
+            }
+        }
+    }
+    __device__ __forceinline__ V first_get(int slot) const { return pre[slot]; }
+    template <int L, int TPL, int R> __device__ __forceinline__ void prefetch_next()
+    {
+        if (has_next) load_first<L, TPL, R>(nin, nvalid);
+    }
+    __device__ __forceinline__ V lds_get(int idx) const
+    {
+        const N2 r = KIND == 0 ? lds[lds_pad(idx)] : lds[idx * rs];
+        return V{r.x, r.y};
+    }
+    __device__ __forceinline__ void lds_put(int idx, V v)
+    {
+        if constexpr (KIND == 0)
+            lds[lds_pad(idx)] = N2{v.x, v.y};
+        else
+            lds[idx * rs] = N2{v.x, v.y};
+    }
     __device__ __forceinline__ void final_put(int idx, V v)
     {
-        if (valid) out[idx] = N2{v.x, v.y};
+        if (!valid) return;
+        if constexpr (KIND == 0)
+            out[idx] = N2{v.x, v.y};
+        else
+            out[(long long)idx * es] = N2{v.x, v.y};
     }
     __device__ __forceinline__ V tw(int e) const
     {
-        N2 r = twd[e];
-        return V{r.x, r.y};
+        if constexpr (TWL) {
+            const N2 r = twl[e];
+            return V{r.x, r.y};
+        } else {
+            N2 r = twg[e];
+            return V{r.x, r.y};
+        }
     }
-    __device__ __forceinline__ void sync() const { wave_sync(); }
+    __device__ __forceinline__ void sync() const
+    {
+        if constexpr (WG)
+            __syncthreads();
+        else
+            wave_sync();
+    }
 };
 
-template <typename T> struct WaveStridedCtx {
-    using V = cx<T>;
-    typedef typename vec2_of<T>::type N2;
-    typedef MIFFT_GLOBAL N2 GN2;
-    static constexpr bool kSyncAfterFirstRead = false;
-    const GN2* in;
-    GN2* out;
-    V* lds; // column ci of the sub-tile: element idx at lds[idx * rs]
-    const GN2* twd;
-    int t;
-    int rs;
-    bool valid;
-    long long es;
-    __device__ __forceinline__ V gload(int idx) const
-    {
-        N2 r = valid ? in[(long long)idx * es] : N2{T(0), T(0)};
-        return V{r.x, r.y};
-    }
-    __device__ __forceinline__ V lds_get(int idx) const { return lds[idx * rs]; }
-    __device__ __forceinline__ void lds_put(int idx, V v) { lds[idx * rs] = v; }
-    __device__ __forceinline__ void final_put(int idx, V v)
-    {
-        if (valid) out[(long long)idx * es] = N2{v.x, v.y};
-    }
-    __device__ __forceinline__ V tw(int e) const
-    {
-        N2 r = twd[e];
-        return V{r.x, r.y};
-    }
-    __device__ __forceinline__ void sync() const { wave_sync(); }
-};
-
-// LDS (elements) one wavefront needs for a sub-tile of length L.
-__host__ __device__ constexpr int batch_wave_lds(int L, int tpl)
+// FP32 items keep a copy of the twiddle table in LDS and prefetch the next
+// sub-tile or tile where its first-stage elements fit in 32 VGPRs; FP64
+// items read twiddles from global memory and do not prefetch (register and
+// LDS budget).
+#ifndef MIFFT_BATCH_TWL
+#define MIFFT_BATCH_TWL 1
+#endif
+#ifndef MIFFT_BATCH_PF
+#define MIFFT_BATCH_PF 1
+#endif
+#ifndef MIFFT_BATCH_WPE
+#define MIFFT_BATCH_WPE 4
+#endif
+template <typename T> constexpr bool batch_tw_in_lds() { return MIFFT_BATCH_TWL && sizeof(T) == 4; }
+template <typename T, int L> constexpr bool batch_prefetches()
 {
-    const int per = 64 / tpl;
-    const int a = (per + 1) * lds_padded_len(L); // contiguous lines + a dummy line
-    const int b = L * (per + 1);                 // columns + a dummy column
-    return a > b ? a : b;
+    using S = FirstStageShape<L, threads_per_line(L, 0, 1), FirstRadix<typename RL<L, 0>::type>::value>;
+    return MIFFT_BATCH_PF && sizeof(T) == 4 && S::SLOTS * sizeof(cx<T>) <= 128;
+}
+
+// Columns of a workgroup column tile of length L.
+__host__ __device__ constexpr int batch_tile_cols(int tpl) { return kBatchBlock / tpl > 0 ? kBatchBlock / tpl : 1; }
+
+// LDS (elements) of one wavefront's z sub-tile of length L (contiguous lines
+// plus a dummy line, then, with tw_lds, the twiddle table) and of a
+// workgroup column tile (columns plus a dummy column, then the table).
+__host__ __device__ constexpr int batch_wave_tile(int L, int tpl)
+{
+    return (64 / tpl + (64 % tpl ? 1 : 0)) * lds_padded_len(L); // dummy line only with left-over lanes
+}
+__host__ __device__ constexpr int batch_wave_lds(int L, int tpl, bool tw_lds)
+{
+    return batch_wave_tile(L, tpl) + (tw_lds ? L : 0);
+}
+__host__ __device__ constexpr int batch_col_tile(int L, int tpl)
+{
+    return L * (batch_tile_cols(tpl) + (kBatchBlock % tpl ? 1 : 0)); // dummy column only with left-over threads
+}
+// Dynamic LDS (elements) of a workgroup for a pass of length L: the larger of
+// the two uses, so one size serves both kinds.
+__host__ __device__ constexpr int batch_lds_elems(int L, int tpl, bool tw_lds)
+{
+    const int z = kBatchWaves * batch_wave_lds(L, tpl, tw_lds);
+    const int c = batch_col_tile(L, tpl) + (tw_lds ? L : 0);
+    return z > c ? z : c;
 }
 
 // Scalar copy of the fields a sub-tile needs (every field is uniform).
@@ -209,66 +283,126 @@ __device__ __forceinline__ PassU load_pass(const MIFFT_CONST BatchPass* p)
     return u;
 }
 
+// One code path per length, kept out of line so each gets its own register
+// allocation.  z: the wavefront's sub-tiles first + wave, first + wave + 4,
+// ...; y / x: the workgroup's column tiles first, first + 1, ...
 template <typename T, int L>
-__device__ __forceinline__ void batch_subtile(const PassU& p, const cx<T>* src, cx<T>* dst, int sub,
-                                              int lane, cx<T>* wlds)
+__device__ __noinline__ void batch_item(const BatchPass* pp, const cx<T>* src, cx<T>* dst, int first, int last,
+                                        int wave, int lane, MIFFT_LDS typename vec2_of<T>::type* lds)
 {
     using V = cx<T>;
-    typedef MIFFT_GLOBAL typename vec2_of<T>::type GV;
+    typedef typename vec2_of<T>::type N2;
+    typedef MIFFT_GLOBAL N2 GV;
     constexpr int TPL = threads_per_line(L, 0, 1);
-    constexpr int per = 64 / TPL;
-    const int ui = lane / TPL; // line / column of this lane within the sub-tile
-    const int t = lane - ui * TPL;
+    using RLt = typename RL<L, 0>::type;
+    constexpr int R0 = FirstRadix<RLt>::value;
+    constexpr bool PF = batch_prefetches<T, L>();
+    constexpr bool TWL = batch_tw_in_lds<T>();
+    constexpr int SLOTS = PF ? FirstStageShape<L, TPL, R0>::SLOTS : 0;
+    const PassU p = load_pass((const MIFFT_CONST BatchPass*)pp);
+    const GV* twg = (const GV*)p.tw;
+    typedef MIFFT_LDS N2 LN2;
     if (p.kind == 0) {
-        WaveContigCtx<T> c;
-        const long long line = (long long)sub * per + ui;
-        c.valid = ui < per && line < p.units;
-        c.in = (const GV*)(src + line * L);
-        c.out = (GV*)(dst + line * L);
+        constexpr int per = 64 / TPL;
+        int s = first + wave;
+        if (s >= last) return;
+        LN2* wlds = lds + wave * batch_wave_lds(L, TPL, TWL);
+        LN2* twl = wlds + batch_wave_tile(L, TPL);
+        if constexpr (TWL) {
+            for (int i = lane; i < L; i += 64) twl[i] = twg[i];
+            wave_sync();
+        }
+        const int ui = lane / TPL; // line of this lane within the sub-tile
+        WaveCtx<T, 0, SLOTS, PF, TWL> c;
         c.lds = wlds + (ui < per ? ui : per) * lds_padded_len(L);
-        c.twd = (const GV*)p.tw;
-        c.t = t;
-        LineFFT<T, L, TPL, WaveContigCtx<T>, typename RL<L, 0>::type>::run(c);
+        c.twl = twl;
+        c.twg = twg;
+        c.t = lane - ui * TPL;
+        auto locate = [&](int sub, long long& off) -> bool {
+            const long long line = (long long)sub * per + ui;
+            off = line * L;
+            return ui < per && line < p.units;
+        };
+        long long off = 0;
+        c.valid = locate(s, off);
+        c.in = (const GV*)(src + off);
+        c.out = (GV*)(dst + off);
+        if constexpr (PF) c.template load_first<L, TPL, R0>(c.in, c.valid);
+#pragma nounroll
+        for (;;) {
+            asm volatile("" : "+v"(c.t)); // keep per-element addressing inside the loop
+            const int nx = s + kBatchWaves;
+            c.has_next = nx < last;
+            long long noff = 0;
+            c.nvalid = c.has_next ? locate(nx, noff) : false;
+            c.nin = (const GV*)(src + noff);
+            LineFFT<T, L, TPL, decltype(c), RLt>::run(c);
+            if (!c.has_next) break;
+            wave_sync(); // the next sub-tile's first stage overwrites this wavefront's tile
+            s = nx;
+            c.valid = c.nvalid;
+            c.in = c.nin;
+            c.out = (GV*)(dst + noff);
+        }
     } else {
-        WaveStridedCtx<T> c;
-        const int g = sub / p.subtiles_per_group;
-        const int c0 = (sub - g * p.subtiles_per_group) * per;
-        const int col = c0 + ui;
-        c.valid = ui < per && col < p.cols;
-        const long long base = (long long)g * p.gs + col;
-        c.in = (const GV*)(src + base);
-        c.out = (GV*)(dst + base);
-        c.rs = per + 1;
-        c.lds = wlds + (ui < per ? ui : per);
-        c.twd = (const GV*)p.tw;
+        // column tile: BC adjacent columns, column index fastest across threads
+        constexpr int BC = batch_tile_cols(TPL);
+        const int tid = threadIdx.x;
+        const bool act = tid < BC * TPL;
+        const int col_in = act ? tid % BC : BC;                  // BC: the dummy column
+        const int t = act ? tid / BC : (tid - BC * TPL) % TPL;
+        LN2* twl = lds + batch_col_tile(L, TPL);
+        if constexpr (TWL) {
+            for (int i = tid; i < L; i += kBatchBlock) twl[i] = twg[i];
+            __syncthreads();
+        }
+        WaveCtx<T, 1, SLOTS, PF, TWL, true> c;
+        c.rs = BC + (kBatchBlock % TPL ? 1 : 0);
+        c.lds = lds + col_in;
+        c.twl = twl;
+        c.twg = twg;
         c.t = t;
         c.es = p.es;
-        LineFFT<T, L, TPL, WaveStridedCtx<T>, typename RL<L, 0>::type>::run(c);
-    }
-}
-
-// One code path per length, kept out of line so each gets its own register
-// allocation: the wavefront's sub-tiles first + wave, first + wave + 4, ...
-template <typename T, int L>
-__device__ __noinline__ void batch_item(const BatchPass* pp, const cx<T>* src_g, cx<T>* dst_g, int first,
-                                        int last, int wave, int lane, int lds_off)
-{
-    const PassU p = load_pass((const MIFFT_CONST BatchPass*)pp);
-    const cx<T>* src = src_g;
-    cx<T>* dst = dst_g;
-    cx<T>* wlds = reinterpret_cast<cx<T>*>(mifft_batch_lds) + lds_off;
+        auto locate = [&](int tile, long long& off) -> bool {
+            const int g = tile / p.subtiles_per_group;
+            const int col = (tile - g * p.subtiles_per_group) * BC + col_in;
+            off = (long long)g * p.gs + col;
+            return act && col < p.cols;
+        };
+        int s = first;
+        long long off = 0;
+        c.valid = locate(s, off);
+        c.in = (const GV*)(src + off);
+        c.out = (GV*)(dst + off);
+        if constexpr (PF) c.template load_first<L, TPL, R0>(c.in, c.valid);
 #pragma nounroll
-    for (int s = first + wave; s < last; s += kBatchWaves) batch_subtile<T, L>(p, src, dst, s, lane, wlds);
+        for (;;) {
+            asm volatile("" : "+v"(c.t), "+v"(c.es), "+v"(c.rs));
+            const int nx = s + 1;
+            c.has_next = nx < last;
+            long long noff = 0;
+            c.nvalid = c.has_next ? locate(nx, noff) : false;
+            c.nin = (const GV*)(src + noff);
+            LineFFT<T, L, TPL, decltype(c), RLt>::run(c);
+            if (!c.has_next) break;
+            __syncthreads(); // the next tile's first stage overwrites the LDS tile
+            s = nx;
+            c.valid = c.nvalid;
+            c.in = c.nin;
+            c.out = (GV*)(dst + noff);
+        }
+    }
 }
 
 template <typename T>
 __device__ __forceinline__ void batch_dispatch(int code, const BatchPass* p, const cx<T>* src, cx<T>* dst,
-                                               int first, int last, int wave, int lane, int wlds)
+                                               int first, int last, int wave, int lane,
+                                               MIFFT_LDS typename vec2_of<T>::type* lds)
 {
     switch (code) {
 #define MIFFT_BATCH_CASE(I, LEN)                                                                  \
     case I:                                                                                       \
-        batch_item<T, LEN>(p, src, dst, first, last, wave, lane, wlds);                          \
+        batch_item<T, LEN>(p, src, dst, first, last, wave, lane, lds);                           \
         break;
         MIFFT_BATCH_MENU(MIFFT_BATCH_CASE)
 #undef MIFFT_BATCH_CASE
@@ -324,7 +458,7 @@ __device__ __forceinline__ void batch_publish(int* pass_done, int* stage_done, i
 // the compiler may merge them across the back edge and let the other lanes
 // run the next iteration's barrier before thread 0 has published the next
 // item.  Decisions thread 0 takes reach the other threads through LDS.
-template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchArgs<T> a)
+template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(MIFFT_BATCH_WPE))) void k_batch(BatchArgs<T> a)
 {
     using V = cx<T>;
     __shared__ int s_item, s_abort, s_flush, s_need, s_full, s_npend;
@@ -334,6 +468,10 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
     int* pass_done = a.counters + 1;
     int* abort_flag = a.counters + 1 + a.npass;
     int* stage_done = a.counters + 2 + a.npass;
+    // LDS address of the dynamic LDS, made opaque so that the compiler does not
+    // propagate the symbol into the per-length functions
+    unsigned lds_base = (unsigned)(size_t)(MIFFT_LDS unsigned char*)mifft_batch_lds;
+    asm volatile("" : "+s"(lds_base));
     // thread 0's bookkeeping (registers of thread 0 only)
     int pend_stage = -1; // stage of the pending completions
     int acq_dep = -1;    // last dependency acquired after it had completed
@@ -367,7 +505,6 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
         const int item_start = __builtin_amdgcn_readfirstlane(pp->item_start);
         const int spi = __builtin_amdgcn_readfirstlane(pp->sub_per_item);
         const int subtiles = __builtin_amdgcn_readfirstlane(pp->subtiles);
-        const int wl = __builtin_amdgcn_readfirstlane(batch_wave_lds(pp->L, pp->tpl));
         // 1. thread 0: does this item need an acquire, is its dependency
         //    complete, must the pending completions be published first?
         if (tid == 0) {
@@ -416,10 +553,10 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
         const V* const* ins = reinterpret_cast<const V* const*>(ka + offsetof(BatchArgs<T>, in));
         const V* src = from_in ? ins[xform] : outs[xform];
         V* dst = outs[xform];
-        const int wlds = wave * wl; // this wavefront's slice of the dynamic LDS (elements)
         const int first = (item - item_start) * spi;
         const int last = first + spi < subtiles ? first + spi : subtiles;
-        batch_dispatch<T>(code, pp, src, dst, first, last, wave, lane, wlds);
+        batch_dispatch<T>(code, pp, src, dst, first, last, wave, lane,
+                          (MIFFT_LDS typename vec2_of<T>::type*)(size_t)lds_base);
         // 4. thread 0: note the completion, take the next item
         __syncthreads();
         if (tid == 0) {
