@@ -38,6 +38,7 @@ struct mifft_batch_s {
     // persistent path
     std::vector<mifft::BatchPass> passes;
     mifft::BatchPass* d_passes = nullptr;
+    int* d_item_pass = nullptr; // pass index of every queue item
     int* d_counters = nullptr;
     int ncounters = 0;
     int total_items = 0;
@@ -89,6 +90,7 @@ mifft_batch_s::~mifft_batch_s()
     if (graph) hipGraphDestroy(graph);
     if (cap_stream) hipStreamDestroy(cap_stream);
     if (d_passes) hipFree(d_passes);
+    if (d_item_pass) hipFree(d_item_pass);
     if (d_counters) hipFree(d_counters);
     for (auto& kv : tw) hipFree(kv.second);
     for (auto& kv : plans) mifft_plan_destroy(kv.second);
@@ -242,6 +244,15 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
         b->total_items = start;
         b->ncounters = (int)P.size() + 2 + kBatchStages;
         b->lds = max_lds * esz;
+        std::vector<int> item_pass((size_t)b->total_items);
+        for (size_t k = 0; k < P.size(); ++k)
+            for (int it = 0; it < P[k].nitems; ++it) item_pass[(size_t)P[k].item_start + it] = (int)k;
+        if (hipMalloc(&b->d_item_pass, sizeof(int) * item_pass.size()) != hipSuccess ||
+            hipMemcpy(b->d_item_pass, item_pass.data(), sizeof(int) * item_pass.size(), hipMemcpyHostToDevice) !=
+                hipSuccess) {
+            delete b;
+            return set_error(MIFFT_ERR_NOMEM, "batch item table");
+        }
         if (hipMalloc(&b->d_passes, sizeof(BatchPass) * P.size()) != hipSuccess ||
             hipMalloc(&b->d_counters, sizeof(int) * b->ncounters) != hipSuccess) {
             delete b;
@@ -287,6 +298,7 @@ static int enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t
     if (b->prec == MIFFT_FP64) {
         BatchArgs<double> a{};
         a.passes = b->d_passes;
+        a.item_pass = b->d_item_pass;
         a.npass = (int)b->passes.size();
         a.total_items = b->total_items;
         a.counters = b->d_counters;
@@ -300,6 +312,7 @@ static int enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t
     } else {
         BatchArgs<float> a{};
         a.passes = b->d_passes;
+        a.item_pass = b->d_item_pass;
         a.npass = (int)b->passes.size();
         a.total_items = b->total_items;
         a.counters = b->d_counters;

@@ -85,6 +85,7 @@ struct BatchPass {
 
 template <typename T> struct BatchArgs {
     const BatchPass* passes;
+    const int* item_pass; // pass of every queue item
     int npass;
     int total_items;
     // [0] queue head, [1 + p] completion of pass p, [1 + npass] abort flag,
@@ -418,24 +419,25 @@ __device__ __forceinline__ int batch_dequeue(int* head, int* abort_flag, int tot
     return __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Publish the pending completions of this workgroup (all threads call it,
-// under a uniform condition).  Every wavefront waits for its own stores and
-// releases them at agent scope; after the barrier thread 0 releases once more
-// and adds the counts.
-//
-// The explicit wait after each release makes the L2 write-back complete
-// before the barrier / the counter updates: the compiler drops its own wait
-// after the write-back when no other vector memory operation is outstanding.
+// The explicit wait after the release makes the L2 write-back complete
+// before the counter updates: the compiler drops its own wait after the
+// write-back when no other vector memory operation is outstanding.
 __device__ __forceinline__ void batch_release_agent()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Publish the pending completions of this workgroup (all threads call it,
+// under a uniform condition).  Every wavefront waits until its own stores
+// have reached the L2; after the barrier thread 0 releases at agent scope
+// once for the workgroup (one L2 write-back, not one per wavefront: at the
+// stage boundaries every workgroup publishes at about the same time, and
+// the write-backs queue up) and adds the counts.
 __device__ __forceinline__ void batch_publish(int* pass_done, int* stage_done, int pend_stage, int* s_npend,
                                               const int* s_pend_ctr, const int* s_pend_n)
 {
-    batch_release_agent();
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
         batch_release_agent();
@@ -451,17 +453,19 @@ __device__ __forceinline__ void batch_publish(int* pass_done, int* stage_done, i
     __syncthreads();
 }
 
-// Loop structure: every region that only thread 0 executes (the dequeue, the
-// dependency check and wait, the pending list) sits between two workgroup
-// barriers, and the loop's back edge leaves from a barrier.  With a thread-0
-// region at the end of one iteration and another at the start of the next,
-// the compiler may merge them across the back edge and let the other lanes
-// run the next iteration's barrier before thread 0 has published the next
-// item.  Decisions thread 0 takes reach the other threads through LDS.
+// Loop structure: every region that only thread 0 executes sits between
+// two workgroup barriers, and the loop's back edge leaves from a barrier.
+// With a thread-0 region at the end of one iteration and another at the
+// start of the next, the compiler may merge them across the back edge and
+// let the other lanes run the next iteration's barrier before thread 0 has
+// published the next item.  Thread 0 prepares the next item at the end of
+// the current one (take it from the queue, find its pass, decide whether
+// the pending completions must be published and whether it needs an
+// acquire) and hands the decisions to the other threads through LDS.
 template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(MIFFT_BATCH_WPE))) void k_batch(BatchArgs<T> a)
 {
     using V = cx<T>;
-    __shared__ int s_item, s_abort, s_flush, s_need, s_full, s_npend;
+    __shared__ int s_item, s_pass, s_abort, s_flush, s_need, s_npend;
     __shared__ int s_pend_ctr[kBatchPend], s_pend_n[kBatchPend];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int* head = a.counters;
@@ -476,10 +480,29 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
     int pend_stage = -1; // stage of the pending completions
     int acq_dep = -1;    // last dependency acquired after it had completed
     int acq_stages = 0;  // stages seen complete before an acquire (bit mask)
+    // thread 0: take the next item and decide what must precede it
+    auto prepare = [&]() {
+        const int it = batch_dequeue(head, abort_flag, a.total_items);
+        s_item = it;
+        s_flush = 0;
+        s_need = 0;
+        if (it >= a.total_items) return;
+        const int lo = a.item_pass[it];
+        s_pass = lo;
+        const BatchPass* q = a.passes + lo;
+        const int dep = q->dep, done = q->done;
+        const int need = dep >= 0 && dep != acq_dep && !((acq_stages >> q->dep_stage) & 1);
+        const int ready =
+            !need || __hip_atomic_load(pass_done + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= q->dep_target;
+        int listed = 0;
+        for (int k = 0; k < s_npend; ++k) listed |= s_pend_ctr[k] == done;
+        s_need = need;
+        s_flush = s_npend > 0 && (!ready || q->stage != pend_stage || (s_npend == kBatchPend && !listed));
+    };
     if (tid == 0) {
-        s_item = batch_dequeue(head, abort_flag, a.total_items);
         s_abort = 0;
         s_npend = 0;
+        prepare();
     }
     __syncthreads();
     for (int iter = 0;; ++iter) {
@@ -491,36 +514,16 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
             if (tid == 0) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
-        // pass of this item: the last pass whose first item is <= item
-        int lo = 0, hi = a.npass - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (__builtin_amdgcn_readfirstlane(a.passes[mid].item_start) <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchPass* pp = a.passes + lo;
+        const BatchPass* pp = a.passes + __builtin_amdgcn_readfirstlane(s_pass);
         const int code = __builtin_amdgcn_readfirstlane(pp->code);
         const int from_in = __builtin_amdgcn_readfirstlane(pp->from_in);
         const int xform = __builtin_amdgcn_readfirstlane(pp->xform);
         const int item_start = __builtin_amdgcn_readfirstlane(pp->item_start);
         const int spi = __builtin_amdgcn_readfirstlane(pp->sub_per_item);
         const int subtiles = __builtin_amdgcn_readfirstlane(pp->subtiles);
-        // 1. thread 0: does this item need an acquire, is its dependency
-        //    complete, must the pending completions be published first?
-        if (tid == 0) {
-            const int dep = pp->dep, stage = pp->stage, done = pp->done;
-            const int need = dep >= 0 && dep != acq_dep && !((acq_stages >> pp->dep_stage) & 1);
-            const int ready =
-                !need || __hip_atomic_load(pass_done + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pp->dep_target;
-            int listed = 0;
-            for (int i = 0; i < s_npend; ++i) listed |= s_pend_ctr[i] == done;
-            s_need = need;
-            s_flush = s_npend > 0 && (!ready || stage != pend_stage || (s_npend == kBatchPend && !listed));
-        }
-        __syncthreads();
-        // 2. publish
+        // 1. publish
         if (__builtin_amdgcn_readfirstlane(s_flush)) batch_publish(pass_done, stage_done, pend_stage, &s_npend, s_pend_ctr, s_pend_n);
-        // 3. wait for the dependency and acquire
+        // 2. wait for the dependency and acquire
         if (__builtin_amdgcn_readfirstlane(s_need)) {
             if (tid == 0) {
                 const int dep = pp->dep, target = pp->dep_target, ds = pp->dep_stage;
@@ -545,9 +548,9 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
             __syncthreads();
             if (__builtin_amdgcn_readfirstlane(s_abort)) break;
         }
-        // The pointer slots are read straight from the kernel-argument segment
-        // (a uniform, dynamically indexed load) so the argument block is never
-        // copied to private memory.
+        // 3. the item.  The pointer slots are read straight from the
+        // kernel-argument segment (a uniform, dynamically indexed load) so the
+        // argument block is never copied to private memory.
         const char* ka = (const char*)__builtin_amdgcn_kernarg_segment_ptr();
         V* const* outs = reinterpret_cast<V* const*>(ka + offsetof(BatchArgs<T>, out));
         const V* const* ins = reinterpret_cast<const V* const*>(ka + offsetof(BatchArgs<T>, in));
@@ -557,20 +560,20 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
         const int last = first + spi < subtiles ? first + spi : subtiles;
         batch_dispatch<T>(code, pp, src, dst, first, last, wave, lane,
                           (MIFFT_LDS typename vec2_of<T>::type*)(size_t)lds_base);
-        // 4. thread 0: note the completion, take the next item
+        // 4. thread 0: note the completion, prepare the next item
         __syncthreads();
         if (tid == 0) {
             const int done = pp->done;
-            int i = 0;
-            while (i < s_npend && s_pend_ctr[i] != done) ++i;
-            if (i == s_npend) {
-                s_pend_ctr[i] = done;
-                s_pend_n[i] = 0;
-                s_npend = i + 1;
+            int k = 0;
+            while (k < s_npend && s_pend_ctr[k] != done) ++k;
+            if (k == s_npend) {
+                s_pend_ctr[k] = done;
+                s_pend_n[k] = 0;
+                s_npend = k + 1;
             }
-            s_pend_n[i] += 1;
+            s_pend_n[k] += 1;
             pend_stage = pp->stage;
-            s_item = batch_dequeue(head, abort_flag, a.total_items);
+            prepare();
         }
         __syncthreads(); // the next item is published
     }
