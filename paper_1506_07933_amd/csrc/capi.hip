@@ -425,7 +425,7 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
     if (!plan || !buf || len == 0) return set_error(MIFFT_ERR_INVALID, "NULL argument");
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
     static const char* kn[] = {"contig", "contig_pack", "strided", "strided_unpack", "r2c_z",
-                               "c2r_z",  "poisson",     "pack",    "unpack",         "copy"};
+                               "c2r_z",  "poisson",     "pack",    "unpack",         "copy", "poisson_x"};
     std::string s;
     auto add = [&](const char* tag, const Pass& q) {
         char line[320];
@@ -451,6 +451,7 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
     } else {
         for (const Pass& q : plan->fwd) add("forward", q);
         for (const Pass& q : plan->inv) add("inverse", q);
+        for (const Pass& q : plan->poisson) add("poisson", q);
     }
     snprintf(buf, len, "%s", s.c_str());
     return MIFFT_OK;

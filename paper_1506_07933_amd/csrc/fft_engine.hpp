@@ -309,6 +309,7 @@ template <> struct FirstRadix<RadixList<>> {
     static constexpr int value = 1; // length 1: no stage
 };
 
+
 template <typename T, int L, int TPL, typename Ctx, typename RL> struct LineFFT;
 template <typename T, int L, int TPL, typename Ctx, int... R>
 struct LineFFT<T, L, TPL, Ctx, RadixList<R...>> {

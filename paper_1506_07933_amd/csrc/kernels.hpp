@@ -367,6 +367,123 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
     }
 }
 
+// ------------------------------------------- fused Poisson x-pass
+// The spectral Poisson solve's middle: on every x-line (fixed k1, k2) of the
+// half spectrum, the forward x-FFT, the multiplication by -scale / |k|^2
+// (0 at k = 0; signed k0, k1, non-negative k2; the same expression as the
+// standalone multiply) and the inverse x-FFT, with the line kept in LDS in
+// between: one read and one write of the spectrum instead of three of each.
+// Column col of group g is (k1, k2) = (g + col / nc, col % nc), which covers
+// both the transposed intermediate (groups = k1, columns = k2) and the
+// standard layout (one group, columns = k1 nc + k2).
+template <typename T> struct PoissonXArgs {
+    cx<T>* data; // in place
+    const cx<T>* tw;
+    int B;
+    int log2B;
+    int cols;
+    int tiles_per_group;
+    long long gs, es;
+    int n1, nc;
+    T scale;
+};
+
+// PHASE 0: the forward transform; the first stage reads global memory and
+// the last stage writes its results (scaled, and conjugated for the
+// inverse) back into the LDS tile -- safe, because every stage after the
+// first synchronises between reading its inputs from the tile and writing.
+// PHASE 1: the inverse transform (of the conjugate) reads the line from LDS
+// and stores the conjugate of its result.
+template <typename T, int PHASE> struct PoissonCtx {
+    using V = cx<T>;
+    static constexpr bool kSyncAfterFirstRead = PHASE == 1; // the first stage reads the LDS tile
+    V* __restrict__ data;
+    V* lds; // column c of the tile: element idx at lds[idx * B]
+    const V* twd;
+    int t;
+    int B;
+    bool valid;
+    long long es;
+    // PHASE 0
+    int n0;
+    long long kk12; // k1^2 + k2^2 of this column
+    T scale;
+
+    __device__ __forceinline__ V gload(int idx) const
+    {
+        if constexpr (PHASE == 0)
+            return valid ? data[(long long)idx * es] : V{T(0), T(0)};
+        else
+            return lds[idx * B];
+    }
+    __device__ __forceinline__ V lds_get(int idx) const { return lds[idx * B]; }
+    __device__ __forceinline__ void lds_put(int idx, V v) { lds[idx * B] = v; }
+    __device__ __forceinline__ void final_put(int idx, V v)
+    {
+        if constexpr (PHASE == 0) {
+            const long long k0 = (2 * idx < n0) ? idx : idx - n0;
+            const long long kk = k0 * k0 + kk12;
+            if (kk == 0) {
+                v = V{T(0), T(0)};
+            } else {
+                const T f = -scale / (T)kk;
+                v.x *= f;
+                v.y *= f;
+            }
+            v.y = -v.y; // the inverse runs as conj(F(conj(.)))
+            lds[idx * B] = v;
+        } else {
+            if (!valid) return;
+            v.y = -v.y;
+            data[(long long)idx * es] = v;
+        }
+    }
+    __device__ __forceinline__ V tw(int e) const { return twd[e]; }
+    __device__ __forceinline__ void sync() const { __syncthreads(); }
+};
+
+template <typename T, int L, int P, int TPL>
+__global__ __launch_bounds__(1024) void k_strided_poisson(PoissonXArgs<T> a)
+{
+    using V = cx<T>;
+    using RLt = typename RL<L, P>::type;
+    extern __shared__ unsigned char smem_raw[];
+    V* smem = reinterpret_cast<V*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int cc = tid & (a.B - 1);
+    const int t = tid >> a.log2B;
+    const int tile = blockIdx.x;
+    const int g = tile / a.tiles_per_group;
+    const int col = (tile - g * a.tiles_per_group) * a.B + cc;
+    const V* twd = stage_twiddles<T>(a.tw, L, smem + a.B * L);
+    PoissonCtx<T, 0> c0;
+    c0.valid = col < a.cols;
+    c0.data = a.data + (long long)g * a.gs + col;
+    c0.lds = smem + cc;
+    c0.twd = twd;
+    c0.t = t;
+    c0.B = a.B;
+    c0.es = a.es;
+    c0.n0 = L;
+    {
+        const int k1i = g + col / a.nc, k2 = col % a.nc;
+        const long long k1 = (2 * k1i < a.n1) ? k1i : k1i - a.n1;
+        c0.kk12 = k1 * k1 + (long long)k2 * k2;
+    }
+    c0.scale = a.scale;
+    LineFFT<T, L, TPL, decltype(c0), RLt>::run(c0);
+    __syncthreads(); // the scaled spectrum of every column is in the tile
+    PoissonCtx<T, 1> c1;
+    c1.valid = c0.valid;
+    c1.data = c0.data;
+    c1.lds = c0.lds;
+    c1.twd = twd;
+    c1.t = t;
+    c1.B = a.B;
+    c1.es = a.es;
+    LineFFT<T, L, TPL, decltype(c1), RLt>::run(c1);
+}
+
 // Lines are mapped as in ContigArgs; offsets count complex elements of the
 // complex side and pairs of reals (complex-sized units) of the real side.
 template <typename T> struct RealArgs {

@@ -316,6 +316,23 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.block), p.shmem, s, a);
         break;
     }
+    case P_POISSON_X: {
+        PoissonXArgs<T> a;
+        a.data = (V*)dst;
+        a.tw = (const V*)p.tw;
+        a.B = p.B;
+        a.log2B = p.log2B;
+        a.cols = p.cols;
+        a.tiles_per_group = p.tiles_per_group;
+        a.gs = p.gs_in;
+        a.es = p.es_in;
+        a.n1 = p.n1;
+        a.nc = p.n2c;
+        a.scale = (T)p.scale;
+        ensure_lds(reinterpret_cast<const void*>(v.poisson_x), p.shmem);
+        hipLaunchKernelGGL(v.poisson_x, dim3(p.grid), dim3(p.block), p.shmem, s, a);
+        break;
+    }
     case P_R2C:
     case P_C2R: {
         RealArgs<T> a;
@@ -753,9 +770,15 @@ int build_plan(Plan& plan, unsigned /*flags*/)
     return MIFFT_OK;
 }
 
-// Poisson (R2C plans): forward into A, multiply, inverse out of A.  Buffers:
-// A = first half of the Poisson workspace, B = the second half (used when
-// the plan runs transposed).
+// Poisson (R2C plans).  Buffers: A = first half of the Poisson workspace,
+// B = the second half.  With n0 > 1 the x-forward, the multiply and the
+// x-inverse run as one fused pass:
+//   transposed:  z (IN -> A), y (A -> B, W[k1][x][k2]), fused x (B),
+//                y^-1 (B, in place on W), z^-1 (B -> OUT, W's line order);
+//   standard:    z (IN -> A), y (A), fused x (A), y^-1 (A), z^-1 (A -> OUT).
+// The inverses then run in the order x, y, z (the x and y inverses act on
+// different axes and commute exactly in exact arithmetic).  Otherwise:
+// forward into A, standalone multiply, inverse out of A.
 void rebuild_poisson(Plan& plan)
 {
     plan.poisson.clear();
@@ -763,9 +786,72 @@ void rebuild_poisson(Plan& plan)
     if (plan.kind != MIFFT_R2C) return;
     const int nc = plan.n2 / 2 + 1;
     const size_t half_bytes = (size_t)plan.n0 * plan.n1 * nc * plan.esz;
+    const double scale = 1.0 / ((double)plan.n0 * plan.n1 * plan.n2);
     auto remap = [](BufId b, BufId in, BufId out, BufId ws) {
         return b == B_IN ? in : b == B_OUT ? out : b == B_WS ? ws : b;
     };
+    const Pass* fx = nullptr; // the forward x-pass
+    for (const Pass& q : plan.fwd)
+        if (q.tag == 2) fx = &q;
+    const int vx = fx ? fx->vidx : -1;
+    const char* unfused = getenv("MIFFT_POISSON_UNFUSED"); // "1": keep the standalone multiply
+    if (plan.n0 > 1 && fx && !(unfused && atoi(unfused) != 0)) {
+        const bool T = plan.transposed;
+        const long long plane = (long long)plan.n1 * nc;
+        Pass z = plan.fwd[0];
+        z.src = B_IN;
+        z.dst = B_SEND;
+        plan.poisson.push_back(z);
+        const BufId D = T ? B_RECV : B_SEND; // where the spectrum sits from the y-pass on
+        if (plan.n1 > 1) {
+            Pass y = plan.fwd[1];
+            y.src = B_SEND;
+            y.dst = D;
+            plan.poisson.push_back(y);
+        }
+        // fused x: the forward x-pass's tile shape, in place
+        Pass x = *fx;
+        x.kind = P_POISSON_X;
+        x.vidx = vx;
+        if (T) {
+            x.es_in = x.es_out = nc;
+            x.gs_in = x.gs_out = (long long)plan.n0 * nc;
+        } else {
+            x.es_in = x.es_out = plane;
+            x.gs_in = x.gs_out = 0;
+        }
+        x.n0 = plan.n0;
+        x.n1 = plan.n1;
+        x.n2c = nc;
+        x.scale = scale;
+        x.tag = 2;
+        x.src = x.dst = D;
+        x.grid = (unsigned)((long long)x.tiles_per_group * x.groups); // one workgroup per tile
+        plan.poisson.push_back(x);
+        if (plan.n1 > 1) {
+            Pass y;
+            const int vy = plan.fwd[1].vidx;
+            // transposed: lines along k1 of W (stride n0 nc); groups = x, columns = k2
+            const int rc = T ? make_strided(plan, y, plan.n1, nc, plan.n0, (long long)plan.n0 * nc, nc, vy, 0)
+                             : make_strided(plan, y, plan.n1, nc, plan.n0, nc, plane, vy, 0);
+            if (rc) { // (only a failed twiddle allocation): fall back to the unfused solve
+                plan.poisson.clear();
+                goto unfused_path;
+            }
+            y.sgn = -1;
+            y.tag = 1;
+            y.src = y.dst = D;
+            plan.poisson.push_back(y);
+        }
+        Pass zi = plan.inv.back(); // C2R, with W's line order when transposed
+        zi.src = D;
+        zi.dst = B_OUT;
+        plan.poisson.push_back(zi);
+        plan.poisson_ws_bytes = 2 * half_bytes;
+        if (plan.poisson_ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.poisson_ws_bytes;
+        return;
+    }
+unfused_path:
     for (Pass q : plan.fwd) { // IN -> A (its OUT), workspace B
         q.src = remap(q.src, B_IN, B_SEND, B_RECV);
         q.dst = remap(q.dst, B_IN, B_SEND, B_RECV);
@@ -776,7 +862,7 @@ void rebuild_poisson(Plan& plan)
     m.n0 = plan.n0;
     m.n1 = plan.n1;
     m.n2c = nc;
-    m.scale = 1.0 / ((double)plan.n0 * plan.n1 * plan.n2);
+    m.scale = scale;
     m.src = m.dst = B_SEND;
     plan.poisson.push_back(m);
     for (Pass q : plan.inv) { // A -> ... -> OUT, workspace B

@@ -25,7 +25,8 @@ enum PassKind {
     P_POISSON,
     P_PACK,
     P_UNPACK,
-    P_COPY
+    P_COPY,
+    P_POISSON_X // fused x-forward, Poisson multiply, x-inverse (in place)
 };
 
 // Which caller buffer a pass reads or writes; resolved at execute time.

@@ -8,6 +8,7 @@ namespace mifft {
 template <typename T> using ContigFn = void (*)(ContigArgs<T>);
 template <typename T> using StridedFn = void (*)(StridedArgs<T>);
 template <typename T> using RealFn = void (*)(RealArgs<T>);
+template <typename T> using PoissonXFn = void (*)(PoissonXArgs<T>);
 
 // One compiled configuration of a line length: its radix policy, the
 // elements-per-thread multiplier and the kernels built from it.
@@ -25,6 +26,7 @@ template <typename T> struct Variant {
     StridedFn<T> strided_split;
     RealFn<T> r2c; // line of 2L reals
     RealFn<T> c2r;
+    PoissonXFn<T> poisson_x; // fused x-forward, multiply, x-inverse
 };
 
 // All variants of this precision (concatenated over the compiled chunks).

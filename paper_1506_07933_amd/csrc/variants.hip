@@ -31,6 +31,7 @@ template <int L, int P, int E> constexpr Variant<MIFFT_REAL> make_variant()
     v.strided_split = &k_strided<MIFFT_REAL, L, P, TPL, true>;
     v.r2c = &k_r2c_z<MIFFT_REAL, L, P, TPL>;
     v.c2r = &k_c2r_z<MIFFT_REAL, L, P, TPL>;
+    v.poisson_x = &k_strided_poisson<MIFFT_REAL, L, P, TPL>;
     return v;
 }
 

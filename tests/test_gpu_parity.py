@@ -262,6 +262,33 @@ def test_poisson_solve(prec, n):
     p.close()
 
 
+@pytest.mark.parametrize("prec,shape", [("fp64", (256, 256, 256)), ("fp32", (256, 256, 256)),
+                                        ("fp64", (64, 48, 32)), ("fp32", (96, 1, 64)),
+                                        ("fp64", (2, 3, 4)), ("fp32", (1, 16, 8))])
+def test_poisson_fused_x_matches_unfused(monkeypatch, prec, shape):
+    """The fused x-forward * multiply * x-inverse schedule (transposed and
+    standard layouts, n1 = 1, tiny and n0 = 1 grids that fall back) against
+    the unfused one with the standalone multiply, and both against the
+    oracle on a general (non-periodic-smooth) right-hand side."""
+    from paper_1506_07933_amd import Plan
+    f = synth.normal_real(shape, RDT[prec], seed=21)
+    f = (f - f.mean(dtype=np.float64)).astype(RDT[prec])
+    ref = oracle.poisson_solve(f.astype(np.float64))
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("MIFFT_POISSON_UNFUSED", mode)
+        p = Plan(shape, "r2c", prec)
+        kinds = [l.split()[1] for l in p.describe().splitlines() if l.startswith("poisson")]
+        print("  ", mode, kinds, flush=True)
+        if mode == "0" and shape[0] > 1:
+            assert "kind=poisson_x" in kinds
+        out[mode] = host(p.poisson(gpu(f)))
+        p.close()
+    report("poisson fused %s %s vs oracle" % (prec, shape), rel_l2(out["0"], ref), TOL[prec])
+    report("poisson unfused %s %s vs oracle" % (prec, shape), rel_l2(out["1"], ref), TOL[prec])
+    report("poisson fused vs unfused %s %s" % (prec, shape), rel_l2(out["0"], out["1"]), TOL[prec])
+
+
 # --------------------------------------------------------- pencil share
 
 def test_cfg3_pencil_share_fused_and_unfused():

@@ -45,7 +45,7 @@ def test_launch_shapes_cover_and_fit(shape, prec, kind):
     passes, ws, _ = plan_only(*shape, kind=kind, prec=prec)
     esz = 16 if prec else 8
     for p in passes:
-        if p["kind"] == "copy":
+        if p["kind"] in ("copy", "poisson"):
             continue
         grid, block, lds = ints(p, "grid", "block", "lds")
         assert 1 <= block <= 1024
@@ -57,6 +57,11 @@ def test_launch_shapes_cover_and_fit(shape, prec, kind):
             # per-line tiles (padded; real kernels hold L + 1 points) + the twiddle table
             n = L if p["kind"] == "contig" else L + 1
             assert lds == (lpw * (n + (n >> 3) + 1) + L) * esz
+        elif p["kind"] == "poisson_x":
+            B, cols, groups, tpl, L = ints(p, "B", "cols", "groups", "tpl", "L")
+            assert B & (B - 1) == 0 and block == B * tpl
+            assert grid == -(-cols // B) * groups
+            assert lds == (B * L + L) * esz
         elif p["kind"] == "strided":
             B, cols, groups, tpl, L = ints(p, "B", "cols", "groups", "tpl", "L")
             assert B & (B - 1) == 0 and block == B * tpl
@@ -140,3 +145,32 @@ def test_pencil_plan_only_describes_fused_stages():
     plan_destroy(h.value)
     assert "pencil_z_pack kind=contig_pack axis=z L=1024" in text
     assert "pencil_unpack_y kind=strided_unpack axis=y L=1024" in text
+
+
+@pytest.mark.parametrize("shape,transposed", [((512, 512, 512), True), ((64, 48, 32), False)])
+def test_poisson_fuses_the_x_passes(shape, transposed):
+    """R2C Poisson: z, y, fused x-forward * multiply * x-inverse, y^-1, z^-1
+    (5 passes, the spectrum read and written once per pass) instead of
+    7 passes plus the standalone multiply."""
+    passes, _, pws = plan_only(*shape, kind=1, prec=0)
+    po = [p for p in passes if p["dir"] == "poisson"]
+    assert [p["kind"] for p in po] == ["r2c_z", "strided", "poisson_x", "strided", "c2r_z"]
+    assert [p["axis"] for p in po] == ["z", "y", "x", "y", "z"]
+    assert [p["sgn"] for p in po][1:4] == ["1", "1", "-1"]
+    n0, n1, n2 = shape
+    nc = n2 // 2 + 1
+    x = po[2]
+    if transposed:   # on W[k1][x][k2]: lines along x (stride nc), groups = k1, columns = k2
+        assert x["es"] == "%d/%d" % (nc, nc) and x["groups"] == str(n1) and x["cols"] == str(nc)
+        assert po[3]["es"] == "%d/%d" % (n0 * nc, n0 * nc) and po[3]["groups"] == str(n0)
+    else:            # standard layout: one group of n1 * nc columns
+        assert x["es"] == "%d/%d" % (n1 * nc, n1 * nc) and x["groups"] == "1"
+        assert x["cols"] == str(n1 * nc)
+    assert pws == 2 * n0 * n1 * nc * 8
+
+
+def test_poisson_unfused_switch(monkeypatch):
+    monkeypatch.setenv("MIFFT_POISSON_UNFUSED", "1")
+    passes, _, _ = plan_only(64, 48, 32, kind=1, prec=1)
+    po = [p["kind"] for p in passes if p["dir"] == "poisson"]
+    assert po == ["r2c_z", "strided", "strided", "poisson", "strided", "strided", "c2r_z"]
