@@ -23,6 +23,23 @@ namespace mifft {
 
 // ------------------------------------------------------------- contexts
 
+// Streaming (non-temporal) stores for the passes' outputs: the next pass
+// reads them gigabytes later, so keeping them in the caches buys nothing.
+#ifndef MIFFT_CONTIG_NT
+#define MIFFT_CONTIG_NT 1
+#endif
+#ifndef MIFFT_STRIDED_NT
+#define MIFFT_STRIDED_NT 1
+#endif
+template <typename T> struct nt2_of;
+template <> struct nt2_of<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct nt2_of<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <typename T> __device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v)
+{
+    typedef typename nt2_of<T>::type N2;
+    __builtin_nontemporal_store(N2{v.x, v.y}, reinterpret_cast<N2*>(p));
+}
+
 template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
     using V = cx<T>;
     static constexpr bool kSyncAfterFirstRead = false;
@@ -51,6 +68,8 @@ template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
         if constexpr (OUT_PACK) {
             uint32_t q = fdiv((uint32_t)idx, pm);
             out[(long long)q * pblk + (idx - (int)(q * pm.d))] = v;
+        } else if constexpr (MIFFT_CONTIG_NT) {
+            store_nt<T>(out + idx, v);
         } else {
             out[idx] = v;
         }
@@ -136,7 +155,10 @@ template <typename T, bool IN_SPLIT, int SLOTS, bool PF> struct StridedCtx {
     {
         if (!valid) return;
         v.y *= sgn;
-        out[(long long)idx * es_out] = v;
+        if constexpr (MIFFT_STRIDED_NT)
+            store_nt<T>(out + (long long)idx * es_out, v);
+        else
+            out[(long long)idx * es_out] = v;
     }
     __device__ __forceinline__ V tw(int e) const { return twd[e]; }
     __device__ __forceinline__ void sync() const { __syncthreads(); }
