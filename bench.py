@@ -82,6 +82,40 @@ def copy_mode(args):
                       "ms": ms, "GBps": 16 * n / ms / 1e6}), flush=True)
 
 
+def workload_mode(args):
+    """One secondary workload alone (for rocprofv3): the 64 uneven transforms
+    in one persistent graph launch and as per-pass kernels, or 512^3 R2C
+    Poisson solves (FP32 and FP64)."""
+    import numpy as np
+    import torch
+
+    from paper_1506_07933_amd import BatchPlan, Plan, synth
+    time_fn = _timer(torch)
+    out = {"mode": args.mode}
+    if args.mode == "batched":
+        shapes, data = synth.batched_uneven(64, seed=0, dtype=np.complex64)
+        xs = [torch.from_numpy(d).cuda() for d in data]
+        outs = [torch.empty_like(v) for v in xs]
+        bp = BatchPlan(shapes, "fp32")
+        out["persistent_graph_ms"] = time_fn(lambda: bp.forward(xs, outs, graph=True), args.warmup, args.steps)
+        assert not bp.aborted()
+        bk = BatchPlan(shapes, "fp32", mode="kernels")
+        out["per_pass_kernels_ms"] = time_fn(lambda: bk.forward(xs, outs), args.warmup, args.steps)
+        bp.close()
+        bk.close()
+    else:
+        for prec, dt in (("fp32", np.float32), ("fp64", np.float64)):
+            f, _ = synth.poisson_rhs(512, seed=0, dtype=dt)
+            fd = torch.from_numpy(f).cuda()
+            p = Plan((512, 512, 512), "r2c", prec)
+            u = torch.empty_like(fd)
+            ws = torch.empty(p.poisson_ws_bytes, dtype=torch.uint8, device="cuda")
+            out["poisson_512_%s_ms" % prec] = time_fn(lambda: p.poisson(fd, out=u, ws=ws), args.warmup, args.steps)
+            p.close()
+            del fd, u, ws
+    print(json.dumps({k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}), flush=True)
+
+
 def _timer(torch):
     def time_fn(fn, warmup, steps):
         for _ in range(warmup):
@@ -166,7 +200,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--mode", choices=["fft", "copy"], default="fft")
+    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson"], default="fft",
+                    help="copy: plain 1 GiB device copy (counter scaling); batched / poisson: only "
+                         "that secondary workload, for profiling")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -175,6 +211,8 @@ def main():
         sys.exit(2)
     if args.mode == "copy":
         return copy_mode(args)
+    if args.mode in ("batched", "poisson"):
+        return workload_mode(args)
 
     import numpy as np
     import torch

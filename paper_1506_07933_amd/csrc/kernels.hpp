@@ -310,8 +310,9 @@ template <typename T> struct StridedArgs {
     int B;
     int log2B;
     int cols;            // columns per group
-    int tiles_per_group; // ceil(cols / B)
+    int ntiles;
     int groups;
+    int tpg;             // tiles per group; 0: tiles over the flattened (group, column) index
     long long gs_in, gs_out; // group strides
     long long es_in, es_out; // element strides
     T sgn;
@@ -329,9 +330,14 @@ template <typename T, int L, int P, int TPL> constexpr bool strided_prefetches()
     return sizeof(T) == 4 && L > 1 && S::SLOTS * sizeof(cx<T>) <= 128;
 }
 
-// Tiles are numbered group-major (tile = group * tiles_per_group + column
-// block); workgroup b takes tiles b, b + grid, b + 2 grid, ... (the grid may
-// be smaller than the number of tiles, never larger).
+// Tiles either stay within a group (tpg tiles per group, the last one
+// ragged when B does not divide cols) or, with tpg = 0, run over the
+// flattened column index f = group * cols + column (tile t holds f = t B ...
+// t B + B - 1, so a tile may span two groups): where one side has gs = cols
+// (the standard layout) its rows are then contiguous and aligned even when
+// cols is not a multiple of B (the 257 columns of a half spectrum).
+// Workgroup b takes tiles b, b + grid, b + 2 grid, ... (the grid may be
+// smaller than the number of tiles, never larger).
 template <typename T, int L, int P, int TPL, bool IN_SPLIT>
 __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
 {
@@ -340,7 +346,7 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
     constexpr int R0 = FirstRadix<RLt>::value;
     using Shape = FirstStageShape<L, TPL, R0>;
     constexpr bool PF = strided_prefetches<T, L, P, TPL>();
-    const int ntiles = a.tiles_per_group * a.groups;
+    const int ntiles = a.ntiles;
     int tile = blockIdx.x;
     if (tile >= ntiles) return; // uniform: the whole workgroup leaves
     extern __shared__ unsigned char smem_raw[];
@@ -357,13 +363,21 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
     c.es_out = a.es_out;
     c.split = a.split;
     c.s_hi = a.s_hi;
-    // column of this thread in a tile; false for the padding columns of a ragged tile
+    // (group, column) of this thread in a tile; false past the last column
     auto locate = [&](int tl, long long& in_off, long long& out_off) -> bool {
-        const int g = tl / a.tiles_per_group;
-        const int col = (tl - g * a.tiles_per_group) * a.B + cc;
+        unsigned g, col;
+        if (a.tpg > 0) {
+            g = (unsigned)tl / (unsigned)a.tpg;
+            col = ((unsigned)tl - g * (unsigned)a.tpg) * (unsigned)a.B + (unsigned)cc;
+            if (col >= (unsigned)a.cols) g = (unsigned)a.groups; // padding column of a ragged tile
+        } else {
+            const unsigned f = (unsigned)tl * (unsigned)a.B + (unsigned)cc;
+            g = f / (unsigned)a.cols;
+            col = f - g * (unsigned)a.cols;
+        }
         in_off = (long long)g * a.gs_in + col;
         out_off = (long long)g * a.gs_out + col;
-        return col < a.cols;
+        return g < (unsigned)a.groups;
     };
     long long io = 0, oo = 0;
     c.valid = locate(tile, io, oo);
@@ -404,7 +418,8 @@ template <typename T> struct PoissonXArgs {
     int B;
     int log2B;
     int cols;
-    int tiles_per_group;
+    int groups;
+    int tpg; // as in StridedArgs
     long long gs, es;
     int n1, nc;
     T scale;
@@ -474,12 +489,20 @@ __global__ __launch_bounds__(1024) void k_strided_poisson(PoissonXArgs<T> a)
     const int tid = threadIdx.x;
     const int cc = tid & (a.B - 1);
     const int t = tid >> a.log2B;
-    const int tile = blockIdx.x;
-    const int g = tile / a.tiles_per_group;
-    const int col = (tile - g * a.tiles_per_group) * a.B + cc;
+    // tiles as in k_strided
+    int g, col;
+    if (a.tpg > 0) {
+        g = (int)blockIdx.x / a.tpg;
+        col = ((int)blockIdx.x - g * a.tpg) * a.B + cc;
+        if (col >= a.cols) g = a.groups; // padding column of a ragged tile
+    } else {
+        const unsigned f = (unsigned)blockIdx.x * (unsigned)a.B + (unsigned)cc;
+        g = (int)(f / (unsigned)a.cols);
+        col = (int)(f - (unsigned)g * (unsigned)a.cols);
+    }
     const V* twd = stage_twiddles<T>(a.tw, L, smem + a.B * L);
     PoissonCtx<T, 0> c0;
-    c0.valid = col < a.cols;
+    c0.valid = g < a.groups;
     c0.data = a.data + (long long)g * a.gs + col;
     c0.lds = smem + cc;
     c0.twd = twd;

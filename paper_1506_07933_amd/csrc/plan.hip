@@ -216,8 +216,8 @@ void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int group
     p.log2B = ilog2(B);
     p.cols = cols;
     p.groups = groups;
-    p.tiles_per_group = (cols + B - 1) / B;
-    p.grid = (unsigned)((long long)p.tiles_per_group * groups);
+    p.ntiles = (int)(((long long)groups * cols + B - 1) / B);
+    p.grid = (unsigned)p.ntiles;
     p.block = (unsigned)(B * tpl);
     p.shmem = ((size_t)B * L + L) * esz; // tile + the staged twiddle table
 }
@@ -239,9 +239,28 @@ static void ensure_lds(const void* fn, size_t bytes)
         cur = bytes;
 }
 
+void tile_pass(const Plan& plan, Pass& p)
+{
+    if (p.kind != P_STRIDED && p.kind != P_STRIDED_SPLIT && p.kind != P_POISSON_X) return;
+    const bool flat = p.gs_out == p.cols || (p.kind != P_STRIDED_SPLIT && p.gs_in == p.cols);
+    p.tpg = flat ? 0 : (p.cols + p.B - 1) / p.B;
+    p.ntiles = flat ? (int)(((long long)p.groups * p.cols + p.B - 1) / p.B) : p.groups * p.tpg;
+    if (p.kind == P_POISSON_X)
+        p.grid = (unsigned)p.ntiles; // one workgroup per tile
+    else
+        strided_grid(plan, p);
+}
+
+void tile_passes(Plan& plan)
+{
+    for (auto* list : {&plan.fwd, &plan.inv, &plan.poisson})
+        for (Pass& p : *list) tile_pass(plan, p);
+    for (Pass* p : {&plan.py, &plan.py_split}) tile_pass(plan, *p);
+}
+
 void strided_grid(const Plan& plan, Pass& p)
 {
-    const long long ntiles = (long long)p.tiles_per_group * p.groups;
+    const long long ntiles = p.ntiles;
     p.grid = (unsigned)ntiles;
     if (const char* e = getenv("MIFFT_STRIDED_PERSIST"))
         if (atoi(e) == 0) return;
@@ -302,8 +321,9 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.B = p.B;
         a.log2B = p.log2B;
         a.cols = p.cols;
-        a.tiles_per_group = p.tiles_per_group;
+        a.ntiles = p.ntiles;
         a.groups = p.groups;
+        a.tpg = p.tpg;
         a.gs_in = p.gs_in;
         a.gs_out = p.gs_out;
         a.es_in = p.es_in;
@@ -323,7 +343,8 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.B = p.B;
         a.log2B = p.log2B;
         a.cols = p.cols;
-        a.tiles_per_group = p.tiles_per_group;
+        a.groups = p.groups;
+        a.tpg = p.tpg;
         a.gs = p.gs_in;
         a.es = p.es_in;
         a.n1 = p.n1;
@@ -527,6 +548,7 @@ static Pass group_chunk(const Plan& plan, const Pass& p, int g0, int ng, size_t 
 {
     Pass q = p;
     q.groups = ng;
+    q.ntiles = (int)(((long long)ng * q.cols + q.B - 1) / q.B);
     strided_grid(plan, q);
     q.off_in = p.off_in + (long long)g0 * p.gs_in * (long long)esz;
     q.off_out = p.off_out + (long long)g0 * p.gs_out * (long long)esz;
@@ -592,6 +614,15 @@ int build_plan(Plan& plan, unsigned /*flags*/)
     const size_t half_bytes = (size_t)n0 * n1 * nc * plan.esz;
     const bool T = want_transposed(plan, nc);
     plan.transposed = T;
+    // Rows of the internal transposed intermediate W are padded to a multiple
+    // of 128 bytes (e.g. 257 -> 272 complex64 for the half spectrum of 512):
+    // with an unaligned pitch every column tile straddles cache lines.
+    int rw = (int)(128 / plan.esz);
+    if (const char* e = getenv("MIFFT_PAD_ROWS")) // "0": unpadded rows (for comparison)
+        if (atoi(e) == 0) rw = 1;
+    const int ncw = (nc + rw - 1) / rw * rw;
+    plan.ncw = ncw;
+    const size_t w_bytes = (size_t)n0 * n1 * ncw * plan.esz;
     const bool has_z = real || n2 > 1;
     int rc, vy = -1, vx = -1, vz = -1;
     if (n1 > 1 && (rc = need_variant(plan, n1, &vy))) return rc;
@@ -617,8 +648,8 @@ int build_plan(Plan& plan, unsigned /*flags*/)
         // tile = (x, B columns of k2); lines along y with stride nc
         if ((rc = make_strided(plan, y, n1, nc, n0, nc, plane, vy, 0))) return rc;
         if (T) {
-            y.es_out = (long long)n0 * nc; // W[k1][x][k2]
-            y.gs_out = nc;
+            y.es_out = (long long)n0 * ncw; // W[k1][x][k2], rows of ncw
+            y.gs_out = ncw;
         }
         y.sgn = +1;
         y.tag = 1;
@@ -627,8 +658,8 @@ int build_plan(Plan& plan, unsigned /*flags*/)
     if (n0 > 1) {
         Pass x;
         if (T) {
-            // tile = (k1, B columns of k2) of W; lines along x with stride nc
-            if ((rc = make_strided(plan, x, n0, nc, n1, nc, (long long)n0 * nc, vx, 0))) return rc;
+            // tile = (k1, B columns of k2) of W; lines along x with stride ncw
+            if ((rc = make_strided(plan, x, n0, nc, n1, ncw, (long long)n0 * ncw, vx, 0))) return rc;
             x.es_out = plane; // standard layout X[k0][k1][k2]
             x.gs_out = nc;
         } else {
@@ -672,15 +703,15 @@ int build_plan(Plan& plan, unsigned /*flags*/)
     if (T) {
         Pass y;
         if ((rc = make_strided(plan, y, n1, nc, n0, nc, plane, vy, 0))) return rc;
-        y.es_out = (long long)n0 * nc;
-        y.gs_out = nc;
+        y.es_out = (long long)n0 * ncw;
+        y.gs_out = ncw;
         y.sgn = -1;
         y.tag = 1;
         y.src = B_IN;
         y.dst = B_WS;
         plan.inv.push_back(y);
         Pass x;
-        if ((rc = make_strided(plan, x, n0, nc, n1, nc, (long long)n0 * nc, vx, 0))) return rc;
+        if ((rc = make_strided(plan, x, n0, nc, n1, ncw, (long long)n0 * ncw, vx, 0))) return rc;
         x.sgn = -1;
         x.tag = 2;
         x.src = x.dst = B_WS;
@@ -697,11 +728,11 @@ int build_plan(Plan& plan, unsigned /*flags*/)
             // contiguous range of lines
             if (real) {
                 if ((rc = make_real_z(plan, z, P_C2R))) return rc;
-                set_line_map(z, n0, (long long)n0 * nc, (long long)nc, (long long)(n2 / 2),
+                set_line_map(z, n0, (long long)n0 * ncw, (long long)ncw, (long long)(n2 / 2),
                              (long long)n1 * (n2 / 2));
             } else {
                 if ((rc = make_contig(plan, z, n2, (long long)n0 * n1, vz))) return rc;
-                set_line_map(z, n0, (long long)n0 * n2, (long long)n2, (long long)n2, (long long)n1 * n2);
+                set_line_map(z, n0, (long long)n0 * ncw, (long long)ncw, (long long)n2, (long long)n1 * n2);
                 z.sgn = -1;
             }
             z.tag = 0;
@@ -763,10 +794,106 @@ int build_plan(Plan& plan, unsigned /*flags*/)
     bool inv_uses_ws = false, fwd_uses_ws = false;
     for (const Pass& q : plan.inv) inv_uses_ws |= (q.src == B_WS || q.dst == B_WS);
     for (const Pass& q : plan.fwd) fwd_uses_ws |= (q.src == B_WS || q.dst == B_WS);
-    plan.ws_bytes = (inv_uses_ws || fwd_uses_ws) ? half_bytes : 0;
+    plan.ws_bytes = (inv_uses_ws || fwd_uses_ws) ? (T ? w_bytes : half_bytes) : 0;
 
     rebuild_poisson(plan);
+    tile_passes(plan);
     if (plan.ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.ws_bytes;
+    return validate_extents(plan);
+}
+
+// ------------------------------------------------------------ extents
+// Every pass's reads and writes, as the largest element offset (plus one)
+// it touches in its source and destination buffers, checked against the
+// buffers' sizes: a plan whose passes could reach past a buffer is an
+// internal error, reported before anything is launched.  Units are
+// complex elements (pairs of reals on the real side).
+struct Extent {
+    long long in, out; // elements, including the pass's byte offsets
+};
+
+static long long line_map_extent(int ni, long long nlines, long long s_o, long long s_i, long long len)
+{
+    if (nlines <= 0) return 0;
+    const long long inner = std::min<long long>(ni, nlines);
+    return ((nlines - 1) / ni) * s_o + (inner - 1) * s_i + len;
+}
+
+static Extent pass_extent(const Pass& p, size_t esz)
+{
+    Extent e{0, 0};
+    const long long oi = p.off_in / (long long)esz, oo = p.off_out / (long long)esz;
+    switch (p.kind) {
+    case P_CONTIG:
+        e.in = oi + line_map_extent(p.ni, p.nlines, p.is_o, p.is_i, p.L);
+        e.out = oo + line_map_extent(p.ni, p.nlines, p.os_o, p.os_i, p.L);
+        break;
+    case P_CONTIG_PACK: {
+        const long long M = p.fd.d;
+        e.in = oi + line_map_extent(p.ni, p.nlines, p.is_o, p.is_i, p.L);
+        e.out = oo + (p.nlines - 1) * M + (p.L / M - 1) * p.blk + M;
+        break;
+    }
+    case P_STRIDED:
+    case P_STRIDED_SPLIT:
+    case P_POISSON_X: {
+        const long long g = p.groups - 1, c = p.cols - 1;
+        if (p.kind == P_STRIDED_SPLIT) {
+            const long long d = p.fd.d;
+            e.in = oi + g * p.gs_in + c + (p.L / d - 1) * p.blk + (d - 1) * p.es_in + 1;
+        } else {
+            e.in = oi + g * p.gs_in + c + (long long)(p.L - 1) * p.es_in + 1;
+        }
+        e.out = oo + g * p.gs_out + c + (long long)(p.L - 1) * p.es_out + 1;
+        break;
+    }
+    case P_R2C: // M pairs in, M + 1 complex out
+        e.in = oi + line_map_extent(p.ni, p.nlines, p.is_o, p.is_i, p.L);
+        e.out = oo + line_map_extent(p.ni, p.nlines, p.os_o, p.os_i, p.L + 1);
+        break;
+    case P_C2R:
+        e.in = oi + line_map_extent(p.ni, p.nlines, p.is_o, p.is_i, p.L + 1);
+        e.out = oo + line_map_extent(p.ni, p.nlines, p.os_o, p.os_i, p.L);
+        break;
+    case P_POISSON:
+        e.in = e.out = (long long)p.n0 * p.n1 * p.n2c;
+        break;
+    default: // pack / unpack / copy: sized by their own plans
+        break;
+    }
+    return e;
+}
+
+int validate_extents(const Plan& plan)
+{
+    if (plan.pencil) return MIFFT_OK;
+    const bool real = plan.kind == MIFFT_R2C;
+    const long long esz = (long long)plan.esz;
+    const long long N = (long long)plan.n0 * plan.n1 * plan.n2;
+    const long long half = (long long)plan.n0 * plan.n1 * (plan.n2 / 2 + 1);
+    const long long sig = real ? N / 2 : N;   // signal side, complex units
+    const long long spec = real ? half : N;   // spectrum side
+    const long long ws = (long long)(plan.ws_bytes / esz);
+    const long long pw = (long long)(plan.poisson_ws_bytes / 2 / esz);
+    struct List {
+        const std::vector<Pass>* v;
+        const char* name;
+        long long in, out;
+    } lists[] = {{&plan.fwd, "forward", sig, spec}, {&plan.inv, "inverse", spec, sig},
+                 {&plan.poisson, "poisson", sig, sig}};
+    for (const List& l : lists) {
+        for (size_t k = 0; k < l.v->size(); ++k) {
+            const Pass& p = (*l.v)[k];
+            const Extent e = pass_extent(p, plan.esz);
+            auto cap = [&](BufId b) -> long long {
+                return b == B_IN ? l.in : b == B_OUT ? l.out : b == B_WS ? ws : (b == B_SEND || b == B_RECV) ? pw : 0;
+            };
+            if ((p.src != B_NONE && e.in > cap(p.src)) || (p.dst != B_NONE && e.out > cap(p.dst)))
+                return set_error(MIFFT_ERR_INVALID,
+                                 "internal: %s pass %zu reaches %lld / %lld elements of buffers holding %lld / %lld",
+                                 l.name, k, e.in, e.out, cap(p.src), cap(p.dst));
+        }
+    }
     return MIFFT_OK;
 }
 
@@ -797,61 +924,75 @@ void rebuild_poisson(Plan& plan)
     const char* unfused = getenv("MIFFT_POISSON_UNFUSED"); // "1": keep the standalone multiply
     if (plan.n0 > 1 && fx && !(unfused && atoi(unfused) != 0)) {
         const bool T = plan.transposed;
-        const long long plane = (long long)plan.n1 * nc;
+        // both buffers are internal: with the transposed intermediate their
+        // rows are padded to ncw (128-byte multiples), as W's are
+        const int pitch = T ? plan.ncw : nc;
+        const long long plane = (long long)plan.n1 * pitch;
+        const int M = plan.n2 / 2;
         Pass z = plan.fwd[0];
+        set_line_map(z, (int)z.nlines, 0, M, 0, pitch); // reals -> A, rows of `pitch`
         z.src = B_IN;
         z.dst = B_SEND;
         plan.poisson.push_back(z);
         const BufId D = T ? B_RECV : B_SEND; // where the spectrum sits from the y-pass on
+        int rc = 0;
         if (plan.n1 > 1) {
-            Pass y = plan.fwd[1];
+            Pass y;
+            rc = make_strided(plan, y, plan.n1, nc, plan.n0, pitch, plane, plan.fwd[1].vidx, 0);
+            if (rc) goto fallback;
+            if (T) { // A -> W[k1][x][k2]
+                y.es_out = (long long)plan.n0 * pitch;
+                y.gs_out = pitch;
+            }
+            y.sgn = +1;
+            y.tag = 1;
             y.src = B_SEND;
             y.dst = D;
             plan.poisson.push_back(y);
         }
-        // fused x: the forward x-pass's tile shape, in place
-        Pass x = *fx;
-        x.kind = P_POISSON_X;
-        x.vidx = vx;
-        if (T) {
-            x.es_in = x.es_out = nc;
-            x.gs_in = x.gs_out = (long long)plan.n0 * nc;
-        } else {
-            x.es_in = x.es_out = plane;
-            x.gs_in = x.gs_out = 0;
+        {
+            // fused x, in place: the forward x-pass's variant and tile shape
+            Pass x;
+            if (T)
+                rc = make_strided(plan, x, plan.n0, nc, plan.n1, pitch, (long long)plan.n0 * pitch, vx, fx->B);
+            else
+                rc = make_strided(plan, x, plan.n0, (int)plane, 1, plane, 0, vx, fx->B);
+            if (rc) goto fallback;
+            x.kind = P_POISSON_X;
+            x.grid = (unsigned)x.ntiles; // one workgroup per tile
+            x.n0 = plan.n0;
+            x.n1 = plan.n1;
+            x.n2c = pitch; // column -> (k1, k2) = (g + col / pitch, col % pitch)
+            x.scale = scale;
+            x.tag = 2;
+            x.src = x.dst = D;
+            plan.poisson.push_back(x);
         }
-        x.n0 = plan.n0;
-        x.n1 = plan.n1;
-        x.n2c = nc;
-        x.scale = scale;
-        x.tag = 2;
-        x.src = x.dst = D;
-        x.grid = (unsigned)((long long)x.tiles_per_group * x.groups); // one workgroup per tile
-        plan.poisson.push_back(x);
         if (plan.n1 > 1) {
             Pass y;
             const int vy = plan.fwd[1].vidx;
-            // transposed: lines along k1 of W (stride n0 nc); groups = x, columns = k2
-            const int rc = T ? make_strided(plan, y, plan.n1, nc, plan.n0, (long long)plan.n0 * nc, nc, vy, 0)
-                             : make_strided(plan, y, plan.n1, nc, plan.n0, nc, plane, vy, 0);
-            if (rc) { // (only a failed twiddle allocation): fall back to the unfused solve
-                plan.poisson.clear();
-                goto unfused_path;
-            }
+            // transposed: lines along k1 of W (stride n0 pitch); groups = x, columns = k2
+            rc = T ? make_strided(plan, y, plan.n1, nc, plan.n0, (long long)plan.n0 * pitch, pitch, vy, 0)
+                   : make_strided(plan, y, plan.n1, nc, plan.n0, pitch, plane, vy, 0);
+            if (rc) goto fallback;
             y.sgn = -1;
             y.tag = 1;
             y.src = y.dst = D;
             plan.poisson.push_back(y);
         }
-        Pass zi = plan.inv.back(); // C2R, with W's line order when transposed
-        zi.src = D;
-        zi.dst = B_OUT;
-        plan.poisson.push_back(zi);
-        plan.poisson_ws_bytes = 2 * half_bytes;
+        {
+            Pass zi = plan.inv.back(); // C2R; with the transposed intermediate, in W's line order
+            if (!T) set_line_map(zi, (int)zi.nlines, 0, pitch, 0, M);
+            zi.src = D;
+            zi.dst = B_OUT;
+            plan.poisson.push_back(zi);
+        }
+        plan.poisson_ws_bytes = 2 * (size_t)plan.n0 * plan.n1 * pitch * plan.esz;
         if (plan.poisson_ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.poisson_ws_bytes;
         return;
+    fallback: // (only a failed twiddle allocation): the unfused solve
+        plan.poisson.clear();
     }
-unfused_path:
     for (Pass q : plan.fwd) { // IN -> A (its OUT), workspace B
         q.src = remap(q.src, B_IN, B_SEND, B_RECV);
         q.dst = remap(q.dst, B_IN, B_SEND, B_RECV);
@@ -870,7 +1011,10 @@ unfused_path:
         q.dst = remap(q.dst, B_SEND, B_OUT, B_RECV);
         plan.poisson.push_back(q);
     }
-    plan.poisson_ws_bytes = 2 * half_bytes;
+    // the two halves are equal: A holds the standard layout, B the (padded)
+    // transposed intermediate
+    const size_t w_bytes = plan.transposed ? (size_t)plan.n0 * plan.n1 * plan.ncw * plan.esz : half_bytes;
+    plan.poisson_ws_bytes = 2 * std::max(half_bytes, w_bytes);
     if (plan.poisson_ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.poisson_ws_bytes;
 }
 
@@ -925,6 +1069,7 @@ int build_pencil(Plan& plan, unsigned /*flags*/)
     plan.pz.tag = plan.pz_pack.tag = 0;
     plan.py.tag = plan.py_split.tag = 1;
     plan.pk.tag = plan.upk.tag = 3;
+    tile_passes(plan);
     return MIFFT_OK;
 }
 

@@ -44,7 +44,8 @@ struct Pass {
     int ni = 1;
     long long is_o = 0, is_i = 0, os_o = 0, os_i = 0;
     // strided passes
-    int B = 1, log2B = 0, cols = 0, tiles_per_group = 0, groups = 0;
+    int B = 1, log2B = 0, cols = 0, ntiles = 0, groups = 0;
+    int tpg = 0; // tiles per group; 0: tiles over the flattened (group, column) index
     long long gs_in = 0, gs_out = 0, es_in = 0, es_out = 0;
     // pack / split
     FastDiv fd{1, 1ull << 32};
@@ -74,6 +75,7 @@ public:
     // The y-pass writes a transposed intermediate W[ky][x][k2] into the
     // workspace so that the x-pass reads with a small stride (see plan.hip).
     bool transposed = false;
+    int ncw = 0; // row pitch (complex elements) of the internal k2 rows: nc rounded up to 128 bytes
     bool plan_only = false; // no device resources: describe only
     int chunks = 1;         // z/y (forward) and x/z (inverse) interleaved in this many chunks
     bool pencil = false;
@@ -119,6 +121,14 @@ void set_contig_geometry(Pass& p, int prec, int tpl, int L, long long nlines, in
 // for kernels that prefetch their next tile, at most as many workgroups as
 // the device holds at once (each then walks tiles with the grid's stride).
 void strided_grid(const Plan& plan, Pass& p);
+// Tiling of a strided / fused-Poisson pass whose strides and tile width are
+// set: tiles over the flattened (group, column) index where either side is
+// contiguous across groups (gs = cols), else per group; then its grid.
+void tile_pass(const Plan& plan, Pass& p);
+void tile_passes(Plan& plan);
+// Every pass's reads and writes stay inside its buffers (MIFFT_OK), or an
+// internal error is set and returned.
+int validate_extents(const Plan& plan);
 void set_line_map(Pass& p, int ni, long long is_o, long long is_i, long long os_o, long long os_i);
 void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int groups, int forceB);
 

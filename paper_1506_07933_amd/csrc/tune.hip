@@ -111,10 +111,9 @@ static bool apply_choice(const Plan& plan, Pass& p, int vidx, int shape)
         p.vidx = vidx;
         p.B = B;
         p.log2B = lg;
-        p.tiles_per_group = (p.cols + B - 1) / B;
         p.block = (unsigned)(B * tpl);
         p.shmem = ((size_t)B * p.L + p.L) * esz;
-        strided_grid(plan, p);
+        tile_pass(plan, p);
         return true;
     }
     const int lpw = shape;
@@ -228,6 +227,8 @@ int tune_plan(Plan& plan)
     if (W) hipFree(W);
     if (tuned_any) save_wisdom_locked();
     if (rc == MIFFT_OK) rebuild_poisson(plan);
+    if (rc == MIFFT_OK) tile_passes(plan);
+    if (rc == MIFFT_OK) rc = validate_extents(plan);
     return rc;
 }
 

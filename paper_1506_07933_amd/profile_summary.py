@@ -21,6 +21,7 @@ import glob
 import json
 import os
 import statistics
+import sys
 
 
 def _csv(d: str, suffix: str):
@@ -58,8 +59,35 @@ def copy_scale(fetch_dir, write_dir, copy_bytes=1 << 30):
     return kib / statistics.mean(f), kib / statistics.mean(w), statistics.mean(f), statistics.mean(w)
 
 
+def stats_table(trace_dir: str, title: str, command: str, note: str = "") -> str:
+    """Markdown table of a rocprofv3 --stats kernel summary (every kernel)."""
+    rows = _csv(trace_dir, "kernel_stats.csv")
+    lines = ["# " + title, "", "Command:", "", "    " + command, ""]
+    if note:
+        lines += [note, ""]
+    lines += ["| kernel | calls | mean us | min us | max us | share |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %.1f%% |" % (
+            r["Name"].split("(")[0], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
+    if len(sys.argv) > 1 and sys.argv[1] == "stats":
+        ap.add_argument("cmd")
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--title", required=True)
+        ap.add_argument("--command", required=True)
+        ap.add_argument("--note", default="")
+        ap.add_argument("--out", required=True)
+        a = ap.parse_args()
+        text = stats_table(a.trace, a.title, a.command, a.note)
+        with open(a.out, "w") as f:
+            f.write(text)
+        print(text)
+        return
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
@@ -113,7 +141,6 @@ def main():
         f.write("\n".join(lines) + "\n")
     if a.traffic_json and traffic:
         here = os.path.dirname(os.path.abspath(__file__))
-        import sys
         sys.path.insert(0, os.path.dirname(here))
         from bench import csrc_hash
         data = {}

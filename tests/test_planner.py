@@ -60,19 +60,26 @@ def test_launch_shapes_cover_and_fit(shape, prec, kind):
         elif p["kind"] == "poisson_x":
             B, cols, groups, tpl, L = ints(p, "B", "cols", "groups", "tpl", "L")
             assert B & (B - 1) == 0 and block == B * tpl
-            assert grid == -(-cols // B) * groups
+            tpg = int(p["tpg"])
+            assert grid == (-(-cols * groups // B) if tpg == 0 else groups * tpg)
             assert lds == (B * L + L) * esz
         elif p["kind"] == "strided":
             B, cols, groups, tpl, L = ints(p, "B", "cols", "groups", "tpl", "L")
             assert B & (B - 1) == 0 and block == B * tpl
-            tiles = -(-cols // B)
+            tpg = int(p["tpg"])
+            # tiles over the flattened (group, column) index where one side is
+            # contiguous across groups (gs = cols), else per group
+            gs_in, gs_out = (int(v) for v in p["gs"].split("/"))
+            assert (tpg == 0) == (gs_out == cols or gs_in == cols)
+            tiles = -(-cols * groups // B) if tpg == 0 else groups * tpg
+            assert int(p["tiles"]) == tiles
             if p["pf"] == "1":
                 # prefetching kernels walk the tiles with a grid of at most one
                 # resident wave of workgroups (256 CUs x workgroups per CU)
                 per_cu = max(1, min(160 * 1024 // lds, 2048 // block))
-                assert grid == min(tiles * groups, 256 * per_cu)
+                assert grid == min(tiles, 256 * per_cu)
             else:
-                assert grid == tiles * groups
+                assert grid == tiles
             assert lds == (B * L + L) * esz  # column tile + the twiddle table
 
 
@@ -123,9 +130,17 @@ def test_small_grid_keeps_standard_layout():
 
 
 def test_r2c_workspace_sizes():
-    _, ws, pws = plan_only(256, 256, 256, kind=1, prec=1)
-    half = 256 * 256 * 129 * 16
-    assert ws == half and pws == 2 * half
+    # transposed intermediate: rows of the half spectrum (129) padded to a
+    # multiple of 128 bytes (136 complex128)
+    passes, ws, pws = plan_only(256, 256, 256, kind=1, prec=1)
+    w = 256 * 256 * 136 * 16
+    assert ws == w and pws == 2 * w
+    fwd = [p for p in passes if p["dir"] == "forward"]
+    assert fwd[1]["es"] == "129/%d" % (256 * 136) and fwd[1]["gs"] == "%d/136" % (256 * 129)
+    assert fwd[2]["es"] == "136/%d" % (256 * 129) and fwd[2]["gs"] == "%d/129" % (256 * 136)
+    # small grids keep the standard layout and the unpadded workspace
+    _, ws, pws = plan_only(32, 32, 32, kind=1, prec=1)
+    assert pws == 2 * 32 * 32 * 17 * 16
 
 
 def test_plan_only_cannot_execute():
@@ -159,14 +174,16 @@ def test_poisson_fuses_the_x_passes(shape, transposed):
     assert [p["sgn"] for p in po][1:4] == ["1", "1", "-1"]
     n0, n1, n2 = shape
     nc = n2 // 2 + 1
+    pitch = -(-nc // 16) * 16 if transposed else nc   # internal rows padded to 128 bytes
     x = po[2]
-    if transposed:   # on W[k1][x][k2]: lines along x (stride nc), groups = k1, columns = k2
-        assert x["es"] == "%d/%d" % (nc, nc) and x["groups"] == str(n1) and x["cols"] == str(nc)
-        assert po[3]["es"] == "%d/%d" % (n0 * nc, n0 * nc) and po[3]["groups"] == str(n0)
+    if transposed:   # on W[k1][x][k2]: lines along x (stride pitch), groups = k1, columns = k2
+        assert x["es"] == "%d/%d" % (pitch, pitch) and x["groups"] == str(n1) and x["cols"] == str(nc)
+        assert po[3]["es"] == "%d/%d" % (n0 * pitch, n0 * pitch) and po[3]["groups"] == str(n0)
+        assert po[1]["es"] == "%d/%d" % (pitch, n0 * pitch)
     else:            # standard layout: one group of n1 * nc columns
         assert x["es"] == "%d/%d" % (n1 * nc, n1 * nc) and x["groups"] == "1"
         assert x["cols"] == str(n1 * nc)
-    assert pws == 2 * n0 * n1 * nc * 8
+    assert pws == 2 * n0 * n1 * pitch * 8
 
 
 def test_poisson_unfused_switch(monkeypatch):
@@ -174,3 +191,29 @@ def test_poisson_unfused_switch(monkeypatch):
     passes, _, _ = plan_only(64, 48, 32, kind=1, prec=1)
     po = [p["kind"] for p in passes if p["dir"] == "poisson"]
     assert po == ["r2c_z", "strided", "strided", "poisson", "strided", "strided", "c2r_z"]
+
+
+EXTENT_SHAPES = [(512, 512, 512), (256, 256, 256), (384, 384, 384), (100, 120, 144), (125, 125, 120),
+                 (1024, 1, 2), (1, 1024, 2), (2, 2, 1024), (96, 1, 64), (3, 5, 8), (64, 64, 1024)]
+
+
+@pytest.mark.parametrize("unfused", ["0", "1"])
+@pytest.mark.parametrize("chunk", ["0", "16"])
+def test_every_pass_stays_inside_its_buffers(monkeypatch, unfused, chunk):
+    """The library validates, at plan time, that the largest offset every
+    pass reads or writes lies inside its source and destination buffers
+    (user arrays, workspace, Poisson halves); a violation fails plan
+    creation with an internal error.  A planted under-sized Poisson
+    workspace (the standard-layout size for the padded intermediate) is
+    rejected this way.  Here: every schedule variant is accepted."""
+    monkeypatch.setenv("MIFFT_POISSON_UNFUSED", unfused)
+    monkeypatch.setenv("MIFFT_CHUNK_MIB", chunk)
+    for shape in EXTENT_SHAPES:
+        for kind in (0, 1):
+            if kind == 1 and shape[2] % 2:
+                continue
+            for prec in (0, 1):
+                h = ctypes.c_void_p()
+                rc = lib.mifft_plan_create(ctypes.byref(h), *shape, kind, prec, MIFFT_PLAN_ONLY)
+                assert rc == 0, (shape, kind, prec, lib.mifft_last_error())
+                plan_destroy(h.value)
