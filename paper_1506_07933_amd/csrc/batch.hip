@@ -43,6 +43,7 @@ struct mifft_batch_s {
     int ncounters = 0;
     int total_items = 0;
     int stage_items[mifft::kBatchStages] = {0, 0, 0};
+    int publish_every = 1 << 30; // completions a workgroup holds at most before publishing
     unsigned grid = 0;
     size_t lds = 0;
     std::map<int, void*> tw;
@@ -155,6 +156,10 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
         std::vector<BatchPass>& P = b->passes;
         std::vector<int> last(count, -1); // index of each transform's latest pass
         size_t max_lds = 0; // dynamic LDS elements of the largest pass
+        if (const char* e = getenv("MIFFT_BATCH_PUBLISH_EVERY")) {
+            const int v = atoi(e);
+            if (v > 0) b->publish_every = v;
+        }
         // data per queue item (MIFFT_BATCH_ITEM_KIB overrides the 64 KiB default)
         size_t item_bytes = 64 * 1024;
         if (const char* e = getenv("MIFFT_BATCH_ITEM_KIB")) {
@@ -303,6 +308,7 @@ static int enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t
         a.total_items = b->total_items;
         a.counters = b->d_counters;
         a.spin_limit = 1u << 22;
+        a.publish_every = b->publish_every;
         for (int k = 0; k < kBatchStages; ++k) a.stage_items[k] = b->stage_items[k];
         for (int t = 0; t < b->count; ++t) {
             a.in[t] = (const cx<double>*)in[t];
@@ -317,6 +323,7 @@ static int enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t
         a.total_items = b->total_items;
         a.counters = b->d_counters;
         a.spin_limit = 1u << 22;
+        a.publish_every = b->publish_every;
         for (int k = 0; k < kBatchStages; ++k) a.stage_items[k] = b->stage_items[k];
         for (int t = 0; t < b->count; ++t) {
             a.in[t] = (const cx<float>*)in[t];

@@ -12,7 +12,8 @@
 // finished in a short pending list and publishes them (one release of its
 // stores, then one counter update per pass and one per stage) only before
 // it waits for anything, when the stage of its next item differs from the
-// pending one, when the list is full, and when it leaves.  On this chip an
+// pending one, when the list is full, after a set number of completions,
+// and when it leaves.  On this chip an
 // agent-scope release writes back the XCD's L2 and an acquire invalidates
 // it, so doing both per item would dominate the run; batched, a workgroup
 // publishes a few times per stage.  Acquires are likewise skipped for a
@@ -48,6 +49,21 @@ constexpr int kBatchBlock = 256;    // threads per workgroup (4 wavefronts)
 constexpr int kBatchWaves = kBatchBlock / 64;
 constexpr int kBatchStages = 3;     // z, y, x
 constexpr int kBatchPend = 16;      // passes in a workgroup's pending completion list
+
+// Build-time choices (measured): twiddle copies in LDS, next-sub-tile
+// prefetch, waves per SIMD of the persistent kernel, streaming stores.
+#ifndef MIFFT_BATCH_TWL
+#define MIFFT_BATCH_TWL 1
+#endif
+#ifndef MIFFT_BATCH_PF
+#define MIFFT_BATCH_PF 1
+#endif
+#ifndef MIFFT_BATCH_WPE
+#define MIFFT_BATCH_WPE 4
+#endif
+#ifndef MIFFT_BATCH_NT
+#define MIFFT_BATCH_NT 0
+#endif
 
 // Line lengths with a code path in the persistent kernel: every length up to
 // 256 with prime factors 2, 3, 5 whose threads per line fit one wavefront.
@@ -93,6 +109,7 @@ template <typename T> struct BatchArgs {
     int* counters;
     int stage_items[kBatchStages]; // items per stage
     unsigned spin_limit;           // bound on the polls of one wait
+    int publish_every;             // publish at the latest after this many completions
     const cx<T>* in[kBatchMax];
     cx<T>* out[kBatchMax];
 };
@@ -185,10 +202,17 @@ template <typename T, int KIND, int SLOTS, bool PF, bool TWL, bool WG = false> s
     __device__ __forceinline__ void final_put(int idx, V v)
     {
         if (!valid) return;
-        if constexpr (KIND == 0)
-            out[idx] = N2{v.x, v.y};
-        else
-            out[(long long)idx * es] = N2{v.x, v.y};
+        if constexpr (MIFFT_BATCH_NT) {
+            if constexpr (KIND == 0)
+                __builtin_nontemporal_store(N2{v.x, v.y}, out + idx);
+            else
+                __builtin_nontemporal_store(N2{v.x, v.y}, out + (long long)idx * es);
+        } else {
+            if constexpr (KIND == 0)
+                out[idx] = N2{v.x, v.y};
+            else
+                out[(long long)idx * es] = N2{v.x, v.y};
+        }
     }
     __device__ __forceinline__ V tw(int e) const
     {
@@ -213,15 +237,6 @@ template <typename T, int KIND, int SLOTS, bool PF, bool TWL, bool WG = false> s
 // sub-tile or tile where its first-stage elements fit in 32 VGPRs; FP64
 // items read twiddles from global memory and do not prefetch (register and
 // LDS budget).
-#ifndef MIFFT_BATCH_TWL
-#define MIFFT_BATCH_TWL 1
-#endif
-#ifndef MIFFT_BATCH_PF
-#define MIFFT_BATCH_PF 1
-#endif
-#ifndef MIFFT_BATCH_WPE
-#define MIFFT_BATCH_WPE 4
-#endif
 template <typename T> constexpr bool batch_tw_in_lds() { return MIFFT_BATCH_TWL && sizeof(T) == 4; }
 template <typename T, int L> constexpr bool batch_prefetches()
 {
@@ -478,6 +493,7 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
     asm volatile("" : "+s"(lds_base));
     // thread 0's bookkeeping (registers of thread 0 only)
     int pend_stage = -1; // stage of the pending completions
+    int pend_items = 0;  // completions pending
     int acq_dep = -1;    // last dependency acquired after it had completed
     int acq_stages = 0;  // stages seen complete before an acquire (bit mask)
     // thread 0: take the next item and decide what must precede it
@@ -497,7 +513,9 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
         int listed = 0;
         for (int k = 0; k < s_npend; ++k) listed |= s_pend_ctr[k] == done;
         s_need = need;
-        s_flush = s_npend > 0 && (!ready || q->stage != pend_stage || (s_npend == kBatchPend && !listed));
+        s_flush = s_npend > 0 && (!ready || q->stage != pend_stage || (s_npend == kBatchPend && !listed) ||
+                                  pend_items >= a.publish_every);
+        if (s_flush) pend_items = 0;
     };
     if (tid == 0) {
         s_abort = 0;
@@ -573,6 +591,7 @@ template <typename T> __global__ __launch_bounds__(kBatchBlock) __attribute__((a
             }
             s_pend_n[k] += 1;
             pend_stage = pp->stage;
+            ++pend_items;
             prepare();
         }
         __syncthreads(); // the next item is published
