@@ -32,7 +32,21 @@
  * are reported identically with or without a GPU.  Kernel faults surface at
  * the caller's next synchronisation, as with any stream API.  The message of
  * the last failing call on the calling thread is returned by
- * mifft_last_error().
+ * mifft_last_error().  Every plan is checked when it is built: each pass's
+ * reads and writes must lie inside the buffers it names (user arrays,
+ * workspace); a plan that fails the check is not created
+ * (MIFFT_ERR_INVALID, "internal: ...") and nothing is launched.
+ *
+ * Environment (read when a plan or batch is created):
+ *   MIFFT_WISDOM              file of tuned choices (MIFFT_TUNE)
+ *   MIFFT_CHUNK_MIB           run z / y chunk by chunk over this many MiB of planes (default 0: off)
+ *   MIFFT_STRIDED_PERSIST=0   one workgroup per column tile instead of a resident grid
+ *   MIFFT_PAD_ROWS=0          unpadded rows in the internal transposed intermediate
+ *   MIFFT_POISSON_UNFUSED=1   Poisson solve with a standalone multiply pass
+ *   MIFFT_BATCH_ITEM_KIB      data per work item of the persistent batch (default 64)
+ *   MIFFT_BATCH_PUBLISH_EVERY publish batch completions after this many items (default: never early)
+ * They select among equivalent schedules (for measurement); results agree
+ * within rounding.
  */
 #ifndef MIFFT_H
 #define MIFFT_H
