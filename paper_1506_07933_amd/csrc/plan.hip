@@ -164,9 +164,10 @@ void set_contig_geometry(Pass& p, int prec, int tpl, int L, long long nlines, in
 {
     const size_t esz = prec == MIFFT_FP64 ? 16 : 8;
     // ~128 threads per workgroup (several small workgroups per CU overlap their
-    // load, exchange and store phases)
+    // load, exchange and store phases), and at least two lines: a workgroup of
+    // one 128-thread line (1024-point lines) ran 25% slower than one of two
     int lpw = 128 / tpl;
-    if (lpw < 1) lpw = 1;
+    if (lpw < 2) lpw = 2;
     while (lpw > 1 && ((size_t)lpw * lds_len + L) * esz > kLdsBudget) lpw /= 2;
     // keep enough workgroups to fill the chip when the batch is small
     while (lpw > 1 && lpw * tpl > 64 && (nlines + lpw - 1) / lpw < 1024) lpw /= 2;
@@ -808,9 +809,6 @@ int build_plan(Plan& plan, unsigned /*flags*/)
 // buffers' sizes: a plan whose passes could reach past a buffer is an
 // internal error, reported before anything is launched.  Units are
 // complex elements (pairs of reals on the real side).
-struct Extent {
-    long long in, out; // elements, including the pass's byte offsets
-};
 
 static long long line_map_extent(int ni, long long nlines, long long s_o, long long s_i, long long len)
 {
@@ -819,7 +817,7 @@ static long long line_map_extent(int ni, long long nlines, long long s_o, long l
     return ((nlines - 1) / ni) * s_o + (inner - 1) * s_i + len;
 }
 
-static Extent pass_extent(const Pass& p, size_t esz)
+Extent pass_extent(const Pass& p, size_t esz)
 {
     Extent e{0, 0};
     const long long oi = p.off_in / (long long)esz, oo = p.off_out / (long long)esz;

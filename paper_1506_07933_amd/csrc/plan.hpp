@@ -129,6 +129,12 @@ void tile_passes(Plan& plan);
 // Every pass's reads and writes stay inside its buffers (MIFFT_OK), or an
 // internal error is set and returned.
 int validate_extents(const Plan& plan);
+// Largest element offset (plus one) a pass reads and writes, including its
+// byte offsets; complex elements (pairs of reals on the real side).
+struct Extent {
+    long long in, out;
+};
+Extent pass_extent(const Pass& p, size_t esz);
 void set_line_map(Pass& p, int ni, long long is_o, long long is_i, long long os_o, long long os_i);
 void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int groups, int forceB);
 

@@ -160,21 +160,30 @@ int tune_plan(Plan& plan)
     const size_t nc = plan.kind == MIFFT_R2C ? plan.n2 / 2 + 1 : plan.n2;
     const size_t cbytes = (size_t)plan.n0 * plan.n1 * nc * plan.esz;
     const size_t rbytes = (size_t)plan.n0 * plan.n1 * plan.n2 * plan.esz / 2;
+    // scratch stand-ins for the caller's arrays and for the workspace (whose
+    // rows may be padded: it can be larger than the arrays)
     const size_t bytes = std::max(cbytes, rbytes) + 256;
+    const size_t wbytes = std::max(bytes, plan.ws_bytes + 256);
     void *A = nullptr, *B = nullptr, *W = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = MIFFT_OK;
     bool tuned_any = false;
     if (hipMalloc(&A, bytes) != hipSuccess || hipMalloc(&B, bytes) != hipSuccess ||
-        hipMalloc(&W, bytes) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(&W, wbytes) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         rc = set_error(MIFFT_ERR_NOMEM, "tuning scratch buffers");
     } else {
         hipMemsetAsync(A, 0, bytes, s);
         hipMemsetAsync(B, 0, bytes, s);
-        hipMemsetAsync(W, 0, bytes, s);
+        hipMemsetAsync(W, 0, wbytes, s);
         auto buf = [&](BufId b) -> void* { return b == B_IN ? A : b == B_WS ? W : B; };
+        // a candidate is launched only if its reads and writes stay inside the scratch
+        auto fits = [&](const Pass& q) {
+            const Extent e = pass_extent(q, plan.esz);
+            auto cap = [&](BufId b) { return (long long)((b == B_WS ? wbytes : bytes) / plan.esz); };
+            return e.in <= cap(q.src) && e.out <= cap(q.dst);
+        };
         for (auto* list : {&plan.fwd, &plan.inv}) {
             for (Pass& p : *list) {
                 if (!is_tunable(p)) continue;
@@ -189,7 +198,7 @@ int tune_plan(Plan& plan)
                 Pass best_pass = p;
                 for (auto [v, shape] : candidates(plan, p)) {
                     Pass q = p;
-                    if (!apply_choice(plan, q, v, shape)) continue;
+                    if (!apply_choice(plan, q, v, shape) || !fits(q)) continue;
                     bool ok = true;
                     for (int w = 0; w < 2 && ok; ++w)
                         ok = launch_pass(q, plan.prec, buf(q.src), buf(q.dst), s) == hipSuccess;

@@ -18,7 +18,9 @@ def test_tuned_plans_parity_and_wisdom(tmp_path):
     wisdom = tmp_path / "wisdom.json"
     os.environ["MIFFT_WISDOM"] = str(wisdom)
     from paper_1506_07933_amd import Plan
-    cases = [((128, 96, 64), "c2c", "fp32"), ((64, 64, 64), "r2c", "fp64"), ((48, 100, 120), "c2c", "fp64")]
+    # (64, 256, 256) R2C runs the transposed intermediate with padded rows
+    cases = [((128, 96, 64), "c2c", "fp32"), ((64, 64, 64), "r2c", "fp64"), ((48, 100, 120), "c2c", "fp64"),
+             ((64, 256, 256), "r2c", "fp32")]
     for shape, kind, prec in cases:
         p = Plan(shape, kind, prec, tune=True)
         print("  tuned", shape, kind, prec, "\n", p.describe(), flush=True)
@@ -30,13 +32,15 @@ def test_tuned_plans_parity_and_wisdom(tmp_path):
             xi = p.inverse(torch.from_numpy(X).cuda()).cpu().numpy()
             assert rel_l2(xi, np.prod(shape) * x.astype(np.complex128)) <= TOL[prec]
         else:
-            x = synth.normal_real(shape, np.float64, seed=2)
+            rd = np.float32 if prec == "fp32" else np.float64
+            x = synth.normal_real(shape, rd, seed=2)
+            x64 = x.astype(np.float64)
             Y = p.forward(torch.from_numpy(x).cuda())
-            assert rel_l2(Y.cpu().numpy(), oracle.fft3d_r2c(x)) <= TOL[prec]
-            assert rel_l2(p.inverse(Y).cpu().numpy(), np.prod(shape) * x) <= TOL[prec]
-            f, _ = synth.poisson_rhs(64, seed=4)
+            assert rel_l2(Y.cpu().numpy(), oracle.fft3d_r2c(x64)) <= TOL[prec]
+            assert rel_l2(p.inverse(Y).cpu().numpy(), np.prod(shape) * x64) <= TOL[prec]
+            f = (x64 - x64.mean()).astype(rd)
             u = p.poisson(torch.from_numpy(f).cuda()).cpu().numpy()
-            assert rel_l2(u, oracle.poisson_solve(f)) <= TOL[prec]
+            assert rel_l2(u, oracle.poisson_solve(f.astype(np.float64))) <= TOL[prec]
         first = p.describe()
         p.close()
         text = wisdom.read_text()
