@@ -864,7 +864,18 @@ Extent pass_extent(const Pass& p, size_t esz)
 
 int validate_extents(const Plan& plan)
 {
-    if (plan.pencil) return MIFFT_OK;
+    if (plan.pencil) { // every buffer of a share holds (N0/p0) (N1/p1) N2 elements
+        const long long n = (long long)(plan.n0 / plan.p0) * (plan.n1 / plan.p1) * plan.n2;
+        const Pass* ps[] = {&plan.pz, &plan.pz_pack, &plan.py, &plan.py_split};
+        const char* names[] = {"z", "z+pack", "y", "unpack+y"};
+        for (int k = 0; k < 4; ++k) {
+            const Extent e = pass_extent(*ps[k], plan.esz);
+            if (e.in > n || e.out > n)
+                return set_error(MIFFT_ERR_INVALID, "internal: pencil %s pass reaches %lld / %lld of %lld elements",
+                                 names[k], e.in, e.out, n);
+        }
+        return MIFFT_OK;
+    }
     const bool real = plan.kind == MIFFT_R2C;
     const long long esz = (long long)plan.esz;
     const long long N = (long long)plan.n0 * plan.n1 * plan.n2;
@@ -1068,7 +1079,7 @@ int build_pencil(Plan& plan, unsigned /*flags*/)
     plan.py.tag = plan.py_split.tag = 1;
     plan.pk.tag = plan.upk.tag = 3;
     tile_passes(plan);
-    return MIFFT_OK;
+    return validate_extents(plan);
 }
 
 } // namespace mifft

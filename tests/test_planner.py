@@ -217,3 +217,15 @@ def test_every_pass_stays_inside_its_buffers(monkeypatch, unfused, chunk):
                 rc = lib.mifft_plan_create(ctypes.byref(h), *shape, kind, prec, MIFFT_PLAN_ONLY)
                 assert rc == 0, (shape, kind, prec, lib.mifft_last_error())
                 plan_destroy(h.value)
+
+
+@pytest.mark.parametrize("shape,grid", [((1024, 1024, 1024), (4, 4)), ((256, 256, 512), (2, 4)),
+                                        ((64, 96, 120), (1, 2)), ((32, 32, 32), (2, 2))])
+def test_pencil_passes_stay_inside_the_share(shape, grid):
+    """Pencil plans are checked the same way: every fused / plain z and y
+    pass stays inside the (N0/p0) x (N1/p1) x N2 buffers of the share."""
+    for prec in (0, 1):
+        h = ctypes.c_void_p()
+        rc = lib.mifft_plan_create_pencil(ctypes.byref(h), *shape, *grid, 0, prec, MIFFT_PLAN_ONLY)
+        assert rc == 0, lib.mifft_last_error()
+        plan_destroy(h.value)
