@@ -14,6 +14,9 @@ Contents
   * ``pencil_pack / pencil_unpack / pencil_share_forward`` -- the pack, loopback
     exchange and unpack maps of the row all-to-all (Sec. 2, pencil paragraph,
     and Algorithm 1, steps 1-3), written as numpy permutations.
+  * ``slab_pack / slab_forward / slab_inverse`` -- the slab decomposition of
+    Algorithm 3 for all tasks at once, the all-to-all done as array copies;
+    ``c2r_z`` is the z-only C2R its inverse ends with.
   * ``brute`` submodule -- the direct O(N^2) DFT used to pin the FFT.
 
 Conventions (readings of the paper, listed in the design notes): forward uses
@@ -66,11 +69,13 @@ def _load():
             lib.oracle_fft_axis.argtypes = [dp, i64, ci, i64, ci]
             lib.oracle_fft3d_r2c.argtypes = [dp, dp, ci, ci, ci]
             lib.oracle_fft3d_c2r.argtypes = [dp, dp, ci, ci, ci]
+            lib.oracle_c2r_z.argtypes = [dp, dp, i64, ci]
             lib.oracle_poisson_half.argtypes = [dp, ci, ci, ci, ctypes.c_double]
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ci
             for f in (lib.oracle_fft1d, lib.oracle_fft3d_c2c, lib.oracle_fft_axis,
-                      lib.oracle_fft3d_r2c, lib.oracle_fft3d_c2r, lib.oracle_poisson_half):
+                      lib.oracle_fft3d_r2c, lib.oracle_fft3d_c2r, lib.oracle_c2r_z,
+                      lib.oracle_poisson_half):
                 f.restype = None
             _lib = lib
     return _lib
@@ -138,6 +143,20 @@ def fft3d_c2r(y, n2: int) -> np.ndarray:
     return out
 
 
+def c2r_z(y, n2: int) -> np.ndarray:
+    """z-only C2R: half lines [..., n2//2+1] -> real lines [..., n2], unscaled,
+    by the C2R definition (imaginary parts at k2 = 0 and, for even n2,
+    k2 = n2/2 discarded); the x and y axes are left alone."""
+    a = _as_c128(y)
+    n2c = a.shape[-1]
+    if n2c != n2 // 2 + 1:
+        raise ValueError("half lines have %d entries, n2=%d needs %d" % (n2c, n2, n2 // 2 + 1))
+    lines = int(np.prod(a.shape[:-1], dtype=np.int64))
+    out = np.empty(a.shape[:-1] + (n2,), dtype=np.float64)
+    _load().oracle_c2r_z(_dptr(a), _dptr(out), lines, n2)
+    return out
+
+
 def poisson_half(yhat, n2: int, scale: float = 1.0) -> np.ndarray:
     """U = -scale * F / |k|^2 on the half spectrum, U[0,0,0] = 0."""
     a = _as_c128(yhat)
@@ -192,3 +211,66 @@ def pencil_share_forward(a, p1: int) -> np.ndarray:
     s = pencil_pack(ahat, p1)
     b = pencil_unpack(s, n1l)
     return fft_axis(b, 1, -1)
+
+
+# ---- slab decomposition (Algorithm 3): P tasks, each holding N0/P x-planes ----
+
+def slab_pack(ahat, p: int) -> np.ndarray:
+    """Send layout of the forward slab transpose: S[j][i0][i1][k2] =
+    Ahat[i0][j*n1l + i1][k2] with n1l = N1/p, so block j holds the y range
+    that task j owns after the exchange (Algorithm 3, step T)."""
+    a = np.asarray(ahat)
+    n0l, n1, nc = a.shape
+    if n1 % p:
+        raise ValueError("p must divide N1")
+    return np.ascontiguousarray(a.reshape(n0l, p, n1 // p, nc).transpose(1, 0, 2, 3))
+
+
+def slab_forward(x, p: int, real: bool = False) -> list:
+    """Algorithm 3, forward, for all p tasks with the all-to-all done as
+    array copies.  Task r holds the slab x[r*N0/p : (r+1)*N0/p]; it computes
+    the 2-D DFTs of its x-planes (z, R2C if `real`, then y), sends block j of
+    its pack to task j, stacks the received blocks in sender order along x
+    (N0 x N1/p x N2c) and finishes with the x-DFT.  Returns the p spectral
+    shares; share j is X[:, j*N1/p : (j+1)*N1/p, :]."""
+    x = np.asarray(x)
+    n0, n1, n2 = x.shape
+    if n0 % p or n1 % p:
+        raise ValueError("p must divide N0 and N1")
+    n0l = n0 // p
+    sends = []
+    for r in range(p):
+        a = x[r * n0l:(r + 1) * n0l]
+        if real:
+            ahat = fft_axis(np.asarray(a, dtype=np.float64), 2, -1)[..., :n2 // 2 + 1]
+        else:
+            ahat = fft_axis(a, 2, -1)
+        ahat = fft_axis(ahat, 1, -1)
+        sends.append(slab_pack(ahat, p))
+    shares = []
+    for j in range(p):
+        b = np.concatenate([sends[s][j] for s in range(p)], axis=0)
+        shares.append(fft_axis(b, 0, -1))
+    return shares
+
+
+def slab_inverse(shares, p: int, n2: int = None) -> list:
+    """Algorithm 3, inverse: each task's N0 x N1/p x N2c share gets the x-IDFT;
+    block r of it (x rows r*N0/p ...) goes to task r, which places the block
+    from task s at y rows s*N1/p ... (the receive map of the pencil unpack),
+    then runs the y-IDFT and the z-IDFT (the z-only C2R when n2 is given).
+    Unscaled.  Returns the p spatial slabs."""
+    if len(shares) != p:
+        raise ValueError("need one share per task")
+    n0 = np.asarray(shares[0]).shape[0]
+    if n0 % p:
+        raise ValueError("p must divide N0")
+    n0l = n0 // p
+    sent = [fft_axis(s, 0, +1) for s in shares]
+    slabs = []
+    for r in range(p):
+        recv = np.stack([sent[s][r * n0l:(r + 1) * n0l] for s in range(p)])
+        a = pencil_unpack(recv, recv.shape[2])
+        a = fft_axis(a, 1, +1)
+        slabs.append(c2r_z(a, n2) if n2 is not None else fft_axis(a, 2, +1))
+    return slabs

@@ -258,16 +258,13 @@ void oracle_fft3d_r2c(const double* in, double* out, int n0, int n1, int n2)
     free(full);
 }
 
-/* 3-D C2R: complex[n0][n1][n2/2+1] -> real[n0][n1][n2], unscaled, the input
- * is left untouched.  Definition in the file header. */
-void oracle_fft3d_c2r(const double* in, double* out, int n0, int n1, int n2)
+/* z-only C2R of `lines` half lines complex[lines][n2/2+1] -> real[lines][n2],
+ * unscaled; the imaginary parts at k2 = 0 and (even n2) k2 = n2/2 are
+ * discarded.  Definition in the file header. */
+void oracle_c2r_z(const double* in, double* out, int64_t lines, int n2)
 {
     int n2c = n2 / 2 + 1;
-    int64_t lines = (int64_t)n0 * n1;
-    cplx* half = (cplx*)malloc(sizeof(cplx) * (size_t)lines * (size_t)n2c);
-    memcpy(half, in, sizeof(cplx) * (size_t)lines * (size_t)n2c);
-    fft_axis(half, 1, n0, (int64_t)n1 * n2c, +1);       /* x-lines */
-    fft_axis(half, (int64_t)n0, n1, (int64_t)n2c, +1);  /* y-lines */
+    const cplx* half = (const cplx*)in;
     cplx* roots = make_roots(n2, +1);
     root_table t = {roots, n2};
 #pragma omp parallel
@@ -292,6 +289,19 @@ void oracle_fft3d_c2r(const double* in, double* out, int n0, int n1, int n2)
         free(work);
     }
     free(roots);
+}
+
+/* 3-D C2R: complex[n0][n1][n2/2+1] -> real[n0][n1][n2], unscaled, the input
+ * is left untouched: x- and y-lines inverse, then the z-only C2R. */
+void oracle_fft3d_c2r(const double* in, double* out, int n0, int n1, int n2)
+{
+    int n2c = n2 / 2 + 1;
+    int64_t lines = (int64_t)n0 * n1;
+    cplx* half = (cplx*)malloc(sizeof(cplx) * (size_t)lines * (size_t)n2c);
+    memcpy(half, in, sizeof(cplx) * (size_t)lines * (size_t)n2c);
+    fft_axis(half, 1, n0, (int64_t)n1 * n2c, +1);       /* x-lines */
+    fft_axis(half, (int64_t)n0, n1, (int64_t)n2c, +1);  /* y-lines */
+    oracle_c2r_z((const double*)half, out, lines, n2);
     free(half);
 }
 

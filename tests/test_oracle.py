@@ -12,6 +12,8 @@ Each pin is chosen so a plausible mistake fails at least one test:
   * the C2R definition written as an explicit cosine sum
   * the Poisson closed form for a sum of Fourier modes
   * the pencil pack / exchange / unpack maps against a textbook 2-D DFT
+  * the slab decomposition (Algorithm 3) for all tasks against the brute
+    force 3-D DFT, its inverse against the C2R cosine sum and N x
 """
 import os
 
@@ -286,6 +288,83 @@ def test_pencil_row_group_emulation():
         b = oracle.pencil_unpack(recv, n1l)
         got = oracle.fft_axis(b, 1, -1)
         assert rel_l2(got, ref[:, :, j * m:(j + 1) * m]) < 1e-13
+
+
+# -------------------------------------------------------------- slab maps
+
+def test_slab_pack_is_the_y_split():
+    a = np.arange(3 * 8 * 5).reshape(3, 8, 5)
+    s = oracle.slab_pack(a, 4)
+    assert s.shape == (4, 3, 2, 5)
+    for j in range(4):
+        np.testing.assert_array_equal(s[j], a[:, 2 * j:2 * j + 2, :])
+    assert sorted(s.ravel().tolist()) == list(range(a.size))
+
+
+@pytest.mark.parametrize("shape,p", [((4, 6, 5), 2), ((6, 6, 4), 3), ((8, 4, 3), 4),
+                                     ((2, 2, 7), 1), ((4, 8, 1), 4)])
+def test_slab_forward_c2c_brute(shape, p):
+    """Shares stacked along y are the full 3-D DFT (brute force): a wrong pack
+    order, a wrong receive order or a missing x-DFT all fail here."""
+    x = _rand_c(shape, 21)
+    shares = oracle.slab_forward(x, p)
+    n1l = shape[1] // p
+    assert all(s.shape == (shape[0], n1l, shape[2]) for s in shares)
+    assert rel_l2(np.concatenate(shares, axis=1), brute_dft3(x, -1)) < 1e-13
+
+
+@pytest.mark.parametrize("shape,p", [((4, 6, 6), 2), ((6, 3, 5), 3), ((4, 4, 2), 4)])
+def test_slab_forward_r2c_brute(shape, p):
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal(shape)
+    shares = oracle.slab_forward(x, p, real=True)
+    ref = brute_dft3(x.astype(np.complex128), -1)[..., :shape[2] // 2 + 1]
+    assert rel_l2(np.concatenate(shares, axis=1), ref) < 1e-13
+
+
+@pytest.mark.parametrize("shape,p", [((4, 6, 5), 2), ((6, 6, 8), 3), ((4, 4, 4), 4)])
+def test_slab_inverse_roundtrip(shape, p):
+    x = _rand_c(shape, 23)
+    back = oracle.slab_inverse(oracle.slab_forward(x, p), p)
+    assert all(b.shape == (shape[0] // p,) + shape[1:] for b in back)
+    assert rel_l2(np.concatenate(back, axis=0), x.size * x) < 1e-13
+
+
+def test_slab_inverse_c2r_cosine_sum():
+    """Non-Hermitian half spectrum through the slab inverse: x- and y-IDFTs as
+    explicit matrices, then the C2R cosine sum (odd and even n2)."""
+    rng = np.random.default_rng(24)
+    for (n0, n1, n2), p in [((4, 6, 8), 2), ((6, 3, 7), 3), ((4, 4, 2), 4)]:
+        h = n2 // 2 + 1
+        y = rng.standard_normal((n0, n1, h)) + 1j * rng.standard_normal((n0, n1, h))
+        n1l = n1 // p
+        shares = [y[:, j * n1l:(j + 1) * n1l, :] for j in range(p)]
+        got = np.concatenate(oracle.slab_inverse(shares, p, n2=n2), axis=0)
+        m0 = np.exp(2j * np.pi * np.outer(np.arange(n0), np.arange(n0)) / n0)
+        m1 = np.exp(2j * np.pi * np.outer(np.arange(n1), np.arange(n1)) / n1)
+        t = np.einsum("bk,akz->abz", m1, np.einsum("ak,kbz->abz", m0, y))
+        c = np.arange(n2)
+        ref = np.repeat(t[:, :, :1].real, n2, axis=2)
+        for k in range(1, (n2 - 1) // 2 + 1):
+            ref += 2 * np.real(t[:, :, k:k + 1] * np.exp(2j * np.pi * k * c / n2))
+        if n2 % 2 == 0 and n2 > 1:
+            ref += t[:, :, n2 // 2:n2 // 2 + 1].real * ((-1.0) ** c)
+        assert rel_l2(got, ref) < 1e-13
+
+
+def test_c2r_z_lines():
+    """The z-only C2R: round trip of real lines (n2 x), and the imaginary parts
+    at k = 0 and k = n2/2 have no effect."""
+    rng = np.random.default_rng(25)
+    for n2 in (1, 2, 7, 8, 30):
+        x = rng.standard_normal((3, 4, n2))
+        half = np.fft.fft(x, axis=2)[..., :n2 // 2 + 1]
+        assert rel_l2(oracle.c2r_z(half, n2), n2 * x) < 1e-13
+        bent = half.copy()
+        bent[..., 0] += 3j
+        if n2 % 2 == 0:
+            bent[..., n2 // 2] -= 2j
+        np.testing.assert_array_equal(oracle.c2r_z(bent, n2), oracle.c2r_z(half, n2))
 
 
 def test_fft_axis_matches_numpy():
