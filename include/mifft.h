@@ -184,6 +184,49 @@ int mifft_execute_pencil_stages(mifft_plan plan, unsigned stage_mask, void* in,
                                 void* sendbuf, void* recvbuf, void* out, void* stream);
 
 /*
+ * mifft_plan_create_slab -- plan one task's share of the slab-decomposed
+ * transform of an N0 x N1 x N2 grid over p tasks (Algorithm 3; Sec. 2, slab
+ * paragraph), C2C or R2C / C2R, FP32 or FP64.  With n0l = N0/p, n1l = N1/p
+ * and N2c = N2 (C2C) or N2/2 + 1 (R2C):
+ *   spatial slab    A[n0l][N1][N2]     (real for R2C), x rows r n0l ... of task r
+ *   spectral share  X[N0][n1l][N2c]    y rows r n1l ... of task r
+ *   send / receive  S, R[p][n0l][n1l][N2c]: block j goes to / came from task j
+ * The complex buffers (out, sendbuf, recvbuf, and `in` of the inverse) all
+ * hold n0l N1 N2c = N0 n1l N2c elements.  Forward stages, in this order:
+ *   Z:    2-D FFT part 1, z-FFT (R2C) of A: in -> out            (in kept)
+ *   Y:    2-D FFT part 2, y-FFT: in place on out; with PACK its
+ *         stores go straight to the send layout out -> sendbuf,
+ *         S[j][i0][i1][k2] = Ahat[i0][j n1l + i1][k2]
+ *   PACK: without Y, the same map as a copy out -> sendbuf
+ *   X:    x-FFT of the received slab recvbuf -> out, where the block
+ *         from task s supplies x rows s n0l ... (no unpack needed)
+ * Inverse stages (mask | MIFFT_SLAB_INVERSE), in this order:
+ *   X:      x-IFFT of X: in -> sendbuf, whose block r (x rows r n0l ...)
+ *           is already contiguous
+ *   UNPACK: A[i0][s n1l + i1][k2] = R[s][i0][i1][k2]: recvbuf -> sendbuf;
+ *           with Y fused into the y-IFFT's loads
+ *   Y:      y-IFFT: in place on sendbuf (without UNPACK)
+ *   Z:      z-IFFT (C2R for R2C plans, imaginary parts of k2 = 0 and N2/2
+ *           discarded): sendbuf -> out; sendbuf is kept
+ * Unscaled in both directions.  The all-to-all between the halves is not
+ * performed here: with p = 1 the caller passes recvbuf == sendbuf
+ * (loopback), otherwise it moves the blocks itself.  Errors: p must divide
+ * N0 and N1 (UNSUPPORTED); the out-of-place stages reject aliased buffers
+ * and an unpack with recvbuf == sendbuf when p > 1 (INVALID).  Flags:
+ * MIFFT_PLAN_ONLY only.  No workspace.
+ */
+#define MIFFT_SLAB_Z 1u
+#define MIFFT_SLAB_Y 2u
+#define MIFFT_SLAB_X 4u
+#define MIFFT_SLAB_PACK 8u       /* forward only */
+#define MIFFT_SLAB_UNPACK 16u    /* inverse only */
+#define MIFFT_SLAB_INVERSE 256u  /* selects the inverse stages */
+int mifft_plan_create_slab(mifft_plan* out, int n0, int n1, int n2, int p, int kind, int prec,
+                           unsigned flags);
+int mifft_execute_slab_stages(mifft_plan plan, unsigned stage_mask, const void* in, void* sendbuf,
+                              void* recvbuf, void* out, void* stream);
+
+/*
  * mifft_poisson_solve -- periodic Poisson solve lap(u) = f on [0, 2 pi)^3
  * with an R2C plan: R2C forward, multiply the half spectrum by
  * -1 / (|k|^2 n0 n1 n2) with the k = 0 mode set to zero (signed wavenumbers

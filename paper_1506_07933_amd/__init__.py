@@ -7,11 +7,11 @@ raises if it is not built.
 """
 import importlib
 
-__all__ = ["Plan", "PencilPlan", "BatchPlan", "MifftError"]
+__all__ = ["Plan", "PencilPlan", "SlabPlan", "BatchPlan", "MifftError"]
 
 
 def __getattr__(name):
-    if name in ("Plan", "PencilPlan", "MifftError"):
+    if name in ("Plan", "PencilPlan", "SlabPlan", "MifftError"):
         return getattr(importlib.import_module(".fft", __name__), name)
     if name == "BatchPlan":
         return importlib.import_module(".batch", __name__).BatchPlan

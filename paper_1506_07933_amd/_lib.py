@@ -16,6 +16,8 @@ MIFFT_C2C, MIFFT_R2C = 0, 1
 MIFFT_FP32, MIFFT_FP64 = 0, 1
 MIFFT_HEURISTIC, MIFFT_TUNE, MIFFT_PLAN_ONLY, MIFFT_BATCH_KERNELS = 0, 1, 2, 4
 MIFFT_STAGE_Z, MIFFT_STAGE_PACK, MIFFT_STAGE_UNPACK, MIFFT_STAGE_Y = 1, 2, 4, 8
+MIFFT_SLAB_Z, MIFFT_SLAB_Y, MIFFT_SLAB_X, MIFFT_SLAB_PACK, MIFFT_SLAB_UNPACK = 1, 2, 4, 8, 16
+MIFFT_SLAB_INVERSE = 256
 STATUS = {0: "MIFFT_OK", 1: "MIFFT_ERR_INVALID", 2: "MIFFT_ERR_UNSUPPORTED",
           3: "MIFFT_ERR_NOMEM", 4: "MIFFT_ERR_DEVICE", 5: "MIFFT_ERR_BADPLAN"}
 
@@ -33,6 +35,8 @@ SIGNATURES = {
     "mifft_last_error": (ctypes.c_char_p, []),
     "mifft_plan_create_pencil": (_i, [_vpp, _i, _i, _i, _i, _i, _i, _i, _u]),
     "mifft_execute_pencil_stages": (_i, [_vp, _u, _vp, _vp, _vp, _vp, _vp]),
+    "mifft_plan_create_slab": (_i, [_vpp, _i, _i, _i, _i, _i, _i, _u]),
+    "mifft_execute_slab_stages": (_i, [_vp, _u, _cvp, _vp, _vp, _vp, _vp]),
     "mifft_poisson_ws_bytes": (_sz, [_vp]),
     "mifft_poisson_solve": (_i, [_vp, _cvp, _vp, _vp, _vp]),
     "mifft_batch_create": (_i, [_vpp, _i, ctypes.POINTER(ctypes.c_int), _i, _i, _u]),

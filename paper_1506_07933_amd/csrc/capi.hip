@@ -203,6 +203,50 @@ int mifft_plan_create_pencil(mifft_plan* out, int n0, int n1, int n2, int p0, in
     return finish_plan(p, out);
 }
 
+int mifft_plan_create_slab(mifft_plan* out, int n0, int n1, int n2, int p, int kind, int prec,
+                           unsigned flags)
+{
+    clear_error();
+    if (!out) return set_error(MIFFT_ERR_INVALID, "out is NULL");
+    int rc = validate_dims(n0, n1, n2, kind, prec);
+    if (rc) return rc;
+    if (p < 1) return set_error(MIFFT_ERR_INVALID, "task count p = %d must be >= 1", p);
+    if (flags & ~(unsigned)MIFFT_PLAN_ONLY)
+        return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x (slab plans take MIFFT_PLAN_ONLY only)", flags);
+    if (n0 % p || n1 % p)
+        return set_error(MIFFT_ERR_UNSUPPORTED, "p = %d does not divide n0 = %d and n1 = %d evenly", p, n0, n1);
+    int dev = 0;
+    const bool plan_only = flags & MIFFT_PLAN_ONLY;
+    if (!plan_only && (rc = check_device(&dev))) return rc;
+    mifft_plan_s* q = new mifft_plan_s();
+    q->plan_only = plan_only;
+    q->n0 = n0;
+    q->n1 = n1;
+    q->n2 = n2;
+    q->slab = true;
+    q->slab_p = p;
+    q->kind = kind;
+    q->prec = prec;
+    q->device = dev;
+    if (!plan_only) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            q->cus = cus;
+    }
+    q->esz = prec == MIFFT_FP64 ? 16 : 8;
+    if ((rc = build_slab(*q, flags))) {
+        delete q;
+        return rc;
+    }
+    if (plan_only) {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        g_live.insert(q);
+        *out = static_cast<mifft_plan>(q);
+        return MIFFT_OK;
+    }
+    return finish_plan(q, out);
+}
+
 int mifft_plan_destroy(mifft_plan plan)
 {
     clear_error();
@@ -220,7 +264,7 @@ const char* mifft_last_error(void) { return last_error_cstr(); }
 size_t mifft_workspace_bytes(mifft_plan plan)
 {
     if (!plan || !is_live(plan)) return 0;
-    return plan->pencil ? 0 : plan->ws_bytes;
+    return (plan->pencil || plan->slab) ? 0 : plan->ws_bytes;
 }
 
 size_t mifft_poisson_ws_bytes(mifft_plan plan)
@@ -271,6 +315,7 @@ static int check_exec(mifft_plan plan, const void* in, void* out, void* ws, bool
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
     if (plan->pencil)
         return set_error(MIFFT_ERR_BADPLAN, "pencil plans run through mifft_execute_pencil_stages");
+    if (plan->slab) return set_error(MIFFT_ERR_BADPLAN, "slab plans run through mifft_execute_slab_stages");
     if (plan->plan_only) return set_error(MIFFT_ERR_BADPLAN, "plan was built with MIFFT_PLAN_ONLY");
     if (!in || !out) return set_error(MIFFT_ERR_INVALID, "in / out must not be NULL");
     if (!aligned16(in) || !aligned16(out))
@@ -320,7 +365,7 @@ int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void*
     clear_error();
     if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
-    if (plan->pencil || plan->kind != MIFFT_R2C)
+    if (plan->pencil || plan->slab || plan->kind != MIFFT_R2C)
         return set_error(MIFFT_ERR_BADPLAN, "the Poisson solve needs an R2C plan");
     if (plan->plan_only) return set_error(MIFFT_ERR_BADPLAN, "plan was built with MIFFT_PLAN_ONLY");
     if (!f || !u) return set_error(MIFFT_ERR_INVALID, "f / u must not be NULL");
@@ -370,6 +415,65 @@ int mifft_execute_pencil_stages(mifft_plan plan, unsigned mask, void* a, void* s
     return run_passes(*plan, list, a, out, nullptr, send, recv, (hipStream_t)stream);
 }
 
+int mifft_execute_slab_stages(mifft_plan plan, unsigned mask, const void* in, void* send, void* recv,
+                              void* out, void* stream)
+{
+    clear_error();
+    if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
+    if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
+    if (!plan->slab) return set_error(MIFFT_ERR_BADPLAN, "not a slab plan");
+    if (plan->plan_only) return set_error(MIFFT_ERR_BADPLAN, "plan was built with MIFFT_PLAN_ONLY");
+    const bool inv = mask & MIFFT_SLAB_INVERSE;
+    const unsigned st = mask & ~(unsigned)MIFFT_SLAB_INVERSE;
+    const unsigned all = MIFFT_SLAB_Z | MIFFT_SLAB_Y | MIFFT_SLAB_X | (inv ? MIFFT_SLAB_UNPACK : MIFFT_SLAB_PACK);
+    if (st == 0 || (st & ~all)) return set_error(MIFFT_ERR_INVALID, "bad stage mask 0x%x", mask);
+    const bool z = st & MIFFT_SLAB_Z, y = st & MIFFT_SLAB_Y, x = st & MIFFT_SLAB_X;
+    const bool pk = st & MIFFT_SLAB_PACK, up = st & MIFFT_SLAB_UNPACK;
+    auto need = [](const void* p, const char* name) {
+        if (!p) return set_error(MIFFT_ERR_INVALID, "%s must not be NULL for the selected stages", name);
+        if (!aligned16(p)) return set_error(MIFFT_ERR_INVALID, "%s must be 16-byte aligned", name);
+        return (int)MIFFT_OK;
+    };
+    int rc;
+    std::vector<Pass> list;
+    if (!inv) { // Z, Y (+PACK), PACK, X
+        if (z && ((rc = need(in, "in")) || (rc = need(out, "out")))) return rc;
+        if ((y || pk) && (rc = need(out, "out"))) return rc;
+        if (pk && (rc = need(send, "sendbuf"))) return rc;
+        if (x && ((rc = need(recv, "recvbuf")) || (rc = need(out, "out")))) return rc;
+        if (z && in == out) return set_error(MIFFT_ERR_INVALID, "the z stage runs out of place: in != out");
+        if (pk && send == out) return set_error(MIFFT_ERR_INVALID, "sendbuf must not be out");
+        if (x && recv == out) return set_error(MIFFT_ERR_INVALID, "recvbuf must not be out");
+        if (z) list.push_back(plan->sz);
+        if (y && pk)
+            list.push_back(plan->sy_pack);
+        else if (y)
+            list.push_back(plan->sy);
+        else if (pk)
+            list.push_back(plan->spk);
+        if (x) list.push_back(plan->sx);
+    } else { // X, UNPACK (+Y), Y, Z
+        if (x && ((rc = need(in, "in")) || (rc = need(send, "sendbuf")))) return rc;
+        if (up && ((rc = need(recv, "recvbuf")) || (rc = need(send, "sendbuf")))) return rc;
+        if (y && (rc = need(send, "sendbuf"))) return rc;
+        if (z && ((rc = need(send, "sendbuf")) || (rc = need(out, "out")))) return rc;
+        if (x && in == send) return set_error(MIFFT_ERR_INVALID, "the x^-1 stage runs out of place: in != sendbuf");
+        // the unpack permutes across tiles: in place only where it is the identity
+        if (up && recv == send && plan->slab_p > 1)
+            return set_error(MIFFT_ERR_INVALID, "recvbuf must not be sendbuf for the unpack when p > 1");
+        if (z && send == out) return set_error(MIFFT_ERR_INVALID, "the z^-1 stage runs out of place: sendbuf != out");
+        if (x) list.push_back(plan->sxi);
+        if (up && y)
+            list.push_back(plan->syi_unpack);
+        else if (up)
+            list.push_back(plan->supk);
+        else if (y)
+            list.push_back(plan->syi);
+        if (z) list.push_back(plan->szi);
+    }
+    return run_passes(*plan, list, in, out, nullptr, send, recv, (hipStream_t)stream);
+}
+
 int mifft_profile_begin(mifft_plan plan, int max_calls)
 {
     clear_error();
@@ -377,7 +481,7 @@ int mifft_profile_begin(mifft_plan plan, int max_calls)
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
     if (max_calls < 1 || max_calls > 100000) return set_error(MIFFT_ERR_INVALID, "max_calls out of range");
     size_t longest = std::max(plan->fwd.size(), std::max(plan->inv.size(), plan->poisson.size()));
-    if (longest < 2) longest = 2;
+    if (longest < 4) longest = 4; // stage calls of pencil and slab plans
     const int stride = (int)longest + 1;
     const size_t need = (size_t)max_calls * stride;
     while (plan->prof_events.size() < need) {
@@ -425,13 +529,15 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
     if (!plan || !buf || len == 0) return set_error(MIFFT_ERR_INVALID, "NULL argument");
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
     static const char* kn[] = {"contig", "contig_pack", "strided", "strided_unpack", "r2c_z",
-                               "c2r_z",  "poisson",     "pack",    "unpack",         "copy", "poisson_x"};
+                               "c2r_z",  "poisson",     "pack",    "unpack",         "copy", "poisson_x",
+                               "strided_pack"};
     std::string s;
     auto add = [&](const char* tag, const Pass& q) {
         char line[480];
         int pol = q.vidx >= 0 ? variant_policy(plan->prec, q.vidx) : -1;
         int tpl = q.vidx >= 0 ? variant_tpl(plan->prec, q.vidx) : 0;
-        const bool strided = q.kind == mifft::P_STRIDED || q.kind == mifft::P_STRIDED_SPLIT;
+        const bool strided = q.kind == mifft::P_STRIDED || q.kind == mifft::P_STRIDED_SPLIT ||
+                             q.kind == mifft::P_STRIDED_OSPLIT;
         int pf = strided && q.vidx >= 0 ? variant_prefetch(plan->prec, q.vidx) : 0;
         snprintf(line, sizeof(line),
                  "%s kind=%s axis=%c L=%d policy=%d tpl=%d sgn=%d lines=%lld lpw=%d B=%d cols=%d groups=%d "
@@ -448,6 +554,17 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
         add("pencil_unpack", plan->upk);
         add("pencil_y", plan->py);
         add("pencil_unpack_y", plan->py_split);
+    } else if (plan->slab) {
+        add("slab_z", plan->sz);
+        add("slab_y", plan->sy);
+        add("slab_y_pack", plan->sy_pack);
+        add("slab_pack", plan->spk);
+        add("slab_x", plan->sx);
+        add("slab_x_inv", plan->sxi);
+        add("slab_unpack", plan->supk);
+        add("slab_y_inv", plan->syi);
+        add("slab_unpack_y_inv", plan->syi_unpack);
+        add("slab_z_inv", plan->szi);
     } else {
         for (const Pass& q : plan->fwd) add("forward", q);
         for (const Pass& q : plan->inv) add("inverse", q);

@@ -7,9 +7,12 @@
 // k_strided  batched 1-D FFTs along a strided axis (the y- and x-passes,
 //            Algorithm 1 steps 3 and 5).  A workgroup owns a tile of B
 //            adjacent columns, so every global access of a line element is a
-//            run of B contiguous complex values.  With IN_SPLIT the loads
+//            run of B contiguous complex values.  With SPLIT = 1 the loads
 //            follow the unpack map of the receive layout (Sec. 2: unpack after
-//            the exchange), which fuses the unpack into the y-pass.
+//            the exchange), which fuses the unpack into the y-pass; with
+//            SPLIT = 2 the stores follow the pack map of a send layout split
+//            along the transformed axis (the slab transpose of Algorithm 3),
+//            which fuses that pack into the y-pass.
 // k_r2c_z    real z-lines: n2 reals are read as n2/2 complex values, FFT'd,
 //            and post-processed into the n2/2+1 outputs of the real DFT.
 // k_c2r_z    the inverse: pre-processing of the n2/2+1 inputs (imaginary
@@ -88,7 +91,7 @@ template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
 // tile + grid, ...).  With PF the first stage's inputs of the next tile are
 // loaded into registers while the current tile finishes (kPrefetch); PF is
 // used where those registers fit next to the transform's own.
-template <typename T, bool IN_SPLIT, int SLOTS, bool PF> struct StridedCtx {
+template <typename T, int SPLIT, int SLOTS, bool PF> struct StridedCtx {
     using V = cx<T>;
     static constexpr bool kSyncAfterFirstRead = false;
     static constexpr bool kPrefetch = PF;
@@ -101,7 +104,9 @@ template <typename T, bool IN_SPLIT, int SLOTS, bool PF> struct StridedCtx {
     bool valid;
     T sgn;
     long long es_in, es_out; // element strides
-    FastDiv split;           // IN_SPLIT: y = q * split.d + rem, address q * s_hi + rem * es_in
+    // SPLIT: element y = q * split.d + rem of a line sits at q * s_hi + rem * es
+    // (es_in for SPLIT = 1 on the load side, es_out for SPLIT = 2 on the store side)
+    FastDiv split;
     long long s_hi;
     V pre[SLOTS];            // first-stage inputs of the current tile
     const V* nin;            // next tile: input column, and whether it is a real column
@@ -112,7 +117,7 @@ template <typename T, bool IN_SPLIT, int SLOTS, bool PF> struct StridedCtx {
     {
         V v{T(0), T(0)};
         if (ok) {
-            if constexpr (IN_SPLIT) {
+            if constexpr (SPLIT == 1) {
                 uint32_t q = fdiv((uint32_t)idx, split);
                 v = base[(long long)q * s_hi + (long long)(idx - (int)(q * split.d)) * es_in];
             } else {
@@ -155,10 +160,17 @@ template <typename T, bool IN_SPLIT, int SLOTS, bool PF> struct StridedCtx {
     {
         if (!valid) return;
         v.y *= sgn;
+        long long o;
+        if constexpr (SPLIT == 2) {
+            uint32_t q = fdiv((uint32_t)idx, split);
+            o = (long long)q * s_hi + (long long)(idx - (int)(q * split.d)) * es_out;
+        } else {
+            o = (long long)idx * es_out;
+        }
         if constexpr (MIFFT_STRIDED_NT)
-            store_nt<T>(out + (long long)idx * es_out, v);
+            store_nt<T>(out + o, v);
         else
-            out[(long long)idx * es_out] = v;
+            out[o] = v;
     }
     __device__ __forceinline__ V tw(int e) const { return twd[e]; }
     __device__ __forceinline__ void sync() const { __syncthreads(); }
@@ -338,7 +350,7 @@ template <typename T, int L, int P, int TPL> constexpr bool strided_prefetches()
 // cols is not a multiple of B (the 257 columns of a half spectrum).
 // Workgroup b takes tiles b, b + grid, b + 2 grid, ... (the grid may be
 // smaller than the number of tiles, never larger).
-template <typename T, int L, int P, int TPL, bool IN_SPLIT>
+template <typename T, int L, int P, int TPL, int SPLIT>
 __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
 {
     using V = cx<T>;
@@ -353,7 +365,7 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
     V* smem = reinterpret_cast<V*>(smem_raw);
     const int tid = threadIdx.x;
     const int cc = tid & (a.B - 1);
-    StridedCtx<T, IN_SPLIT, Shape::SLOTS, PF> c;
+    StridedCtx<T, SPLIT, Shape::SLOTS, PF> c;
     c.lds = smem + cc;
     c.twd = stage_twiddles<T>(a.tw, L, smem + a.B * L);
     c.t = tid >> a.log2B;

@@ -242,8 +242,12 @@ static void ensure_lds(const void* fn, size_t bytes)
 
 void tile_pass(const Plan& plan, Pass& p)
 {
-    if (p.kind != P_STRIDED && p.kind != P_STRIDED_SPLIT && p.kind != P_POISSON_X) return;
-    const bool flat = p.gs_out == p.cols || (p.kind != P_STRIDED_SPLIT && p.gs_in == p.cols);
+    if (p.kind != P_STRIDED && p.kind != P_STRIDED_SPLIT && p.kind != P_STRIDED_OSPLIT &&
+        p.kind != P_POISSON_X)
+        return;
+    // a split side is not contiguous across groups
+    const bool flat = (p.kind != P_STRIDED_OSPLIT && p.gs_out == p.cols) ||
+                      (p.kind != P_STRIDED_SPLIT && p.gs_in == p.cols);
     p.tpg = flat ? 0 : (p.cols + p.B - 1) / p.B;
     p.ntiles = flat ? (int)(((long long)p.groups * p.cols + p.B - 1) / p.B) : p.groups * p.tpg;
     if (p.kind == P_POISSON_X)
@@ -256,7 +260,9 @@ void tile_passes(Plan& plan)
 {
     for (auto* list : {&plan.fwd, &plan.inv, &plan.poisson})
         for (Pass& p : *list) tile_pass(plan, p);
-    for (Pass* p : {&plan.py, &plan.py_split}) tile_pass(plan, *p);
+    for (Pass* p : {&plan.py, &plan.py_split, &plan.sy, &plan.sy_pack, &plan.sx, &plan.sxi, &plan.syi,
+                    &plan.syi_unpack})
+        tile_pass(plan, *p);
 }
 
 void strided_grid(const Plan& plan, Pass& p)
@@ -269,8 +275,9 @@ void strided_grid(const Plan& plan, Pass& p)
     int per_cu = 0;
     if (!plan.plan_only) {
         const void* fn = with_table(plan.prec, [&](const auto& t) {
-            return p.kind == P_STRIDED_SPLIT ? reinterpret_cast<const void*>(t[p.vidx].strided_split)
-                                             : reinterpret_cast<const void*>(t[p.vidx].strided);
+            return reinterpret_cast<const void*>(p.kind == P_STRIDED_SPLIT    ? t[p.vidx].strided_split
+                                                 : p.kind == P_STRIDED_OSPLIT ? t[p.vidx].strided_osplit
+                                                                              : t[p.vidx].strided);
         });
         ensure_lds(fn, p.shmem);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)p.block, p.shmem) != hipSuccess) {
@@ -314,7 +321,8 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         break;
     }
     case P_STRIDED:
-    case P_STRIDED_SPLIT: {
+    case P_STRIDED_SPLIT:
+    case P_STRIDED_OSPLIT: {
         StridedArgs<T> a;
         a.in = (const V*)src;
         a.out = (V*)dst;
@@ -332,7 +340,9 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.sgn = (T)p.sgn;
         a.split = p.fd;
         a.s_hi = p.blk;
-        auto fn = p.kind == P_STRIDED ? v.strided : v.strided_split;
+        auto fn = p.kind == P_STRIDED         ? v.strided
+                  : p.kind == P_STRIDED_SPLIT ? v.strided_split
+                                              : v.strided_osplit;
         ensure_lds(reinterpret_cast<const void*>(fn), p.shmem);
         hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.block), p.shmem, s, a);
         break;
@@ -482,7 +492,7 @@ static int make_strided(Plan& plan, Pass& p, int L, int cols, int groups, long l
     return MIFFT_OK;
 }
 
-static int make_real_z(Plan& plan, Pass& p, PassKind kind)
+static int make_real_z(Plan& plan, Pass& p, PassKind kind, long long nlines)
 {
     const int M = plan.n2 / 2;
     const int vidx = default_variant(plan.prec, M);
@@ -493,8 +503,7 @@ static int make_real_z(Plan& plan, Pass& p, PassKind kind)
     if (rc) return rc;
     rc = get_twiddles(plan, plan.n2, (void**)&p.tw2);
     if (rc) return rc;
-    set_contig_geometry(p, plan.prec, variant_tpl(plan.prec, vidx), M,
-                        (long long)plan.n0 * plan.n1, lds_padded_len(M + 1));
+    set_contig_geometry(p, plan.prec, variant_tpl(plan.prec, vidx), M, nlines, lds_padded_len(M + 1));
     // complex side: lines of M + 1; real side: lines of M pairs
     const long long cl = M + 1, rl = M;
     if (kind == P_R2C)
@@ -634,7 +643,7 @@ int build_plan(Plan& plan, unsigned /*flags*/)
     plan.fwd.clear();
     if (real) {
         Pass z;
-        if ((rc = make_real_z(plan, z, P_R2C))) return rc;
+        if ((rc = make_real_z(plan, z, P_R2C, (long long)plan.n0 * plan.n1))) return rc;
         z.tag = 0;
         plan.fwd.push_back(z);
     } else if (has_z) {
@@ -728,7 +737,7 @@ int build_plan(Plan& plan, unsigned /*flags*/)
             // is line (x, y) of the output, so a range of k1 planes is a
             // contiguous range of lines
             if (real) {
-                if ((rc = make_real_z(plan, z, P_C2R))) return rc;
+                if ((rc = make_real_z(plan, z, P_C2R, (long long)plan.n0 * plan.n1))) return rc;
                 set_line_map(z, n0, (long long)n0 * ncw, (long long)ncw, (long long)(n2 / 2),
                              (long long)n1 * (n2 / 2));
             } else {
@@ -758,7 +767,7 @@ int build_plan(Plan& plan, unsigned /*flags*/)
         }
         if (real) {
             Pass z;
-            if ((rc = make_real_z(plan, z, P_C2R))) return rc;
+            if ((rc = make_real_z(plan, z, P_C2R, (long long)plan.n0 * plan.n1))) return rc;
             z.tag = 0;
             plan.inv.push_back(z);
         } else if (has_z) {
@@ -834,15 +843,17 @@ Extent pass_extent(const Pass& p, size_t esz)
     }
     case P_STRIDED:
     case P_STRIDED_SPLIT:
+    case P_STRIDED_OSPLIT:
     case P_POISSON_X: {
-        const long long g = p.groups - 1, c = p.cols - 1;
-        if (p.kind == P_STRIDED_SPLIT) {
-            const long long d = p.fd.d;
+        const long long g = p.groups - 1, c = p.cols - 1, d = p.fd.d;
+        if (p.kind == P_STRIDED_SPLIT)
             e.in = oi + g * p.gs_in + c + (p.L / d - 1) * p.blk + (d - 1) * p.es_in + 1;
-        } else {
+        else
             e.in = oi + g * p.gs_in + c + (long long)(p.L - 1) * p.es_in + 1;
-        }
-        e.out = oo + g * p.gs_out + c + (long long)(p.L - 1) * p.es_out + 1;
+        if (p.kind == P_STRIDED_OSPLIT)
+            e.out = oo + g * p.gs_out + c + (p.L / d - 1) * p.blk + (d - 1) * p.es_out + 1;
+        else
+            e.out = oo + g * p.gs_out + c + (long long)(p.L - 1) * p.es_out + 1;
         break;
     }
     case P_R2C: // M pairs in, M + 1 complex out
@@ -873,6 +884,28 @@ int validate_extents(const Plan& plan)
             if (e.in > n || e.out > n)
                 return set_error(MIFFT_ERR_INVALID, "internal: pencil %s pass reaches %lld / %lld of %lld elements",
                                  names[k], e.in, e.out, n);
+        }
+        return MIFFT_OK;
+    }
+    if (plan.slab) { // every complex buffer holds (N0/p) N1 N2c elements; the real slab (N0/p) N1 N2/2 pairs
+        const bool real = plan.kind == MIFFT_R2C;
+        const long long nc = real ? plan.n2 / 2 + 1 : plan.n2;
+        const long long n = (long long)(plan.n0 / plan.slab_p) * plan.n1 * nc;
+        const long long r = real ? (long long)(plan.n0 / plan.slab_p) * plan.n1 * (plan.n2 / 2) : n;
+        struct Item {
+            const Pass* p;
+            const char* name;
+            long long in, out;
+        } items[] = {{&plan.sz, "z", r, n},         {&plan.sy, "y", n, n},
+                     {&plan.sy_pack, "y+pack", n, n}, {&plan.sx, "x", n, n},
+                     {&plan.sxi, "x^-1", n, n},      {&plan.syi, "y^-1", n, n},
+                     {&plan.syi_unpack, "unpack+y^-1", n, n}, {&plan.szi, "z^-1", n, r}};
+        for (const Item& it : items) {
+            const Extent e = pass_extent(*it.p, plan.esz);
+            if (e.in > it.in || e.out > it.out)
+                return set_error(MIFFT_ERR_INVALID,
+                                 "internal: slab %s pass reaches %lld / %lld of %lld / %lld elements", it.name,
+                                 e.in, e.out, it.in, it.out);
         }
         return MIFFT_OK;
     }
@@ -1078,6 +1111,99 @@ int build_pencil(Plan& plan, unsigned /*flags*/)
     plan.pz.tag = plan.pz_pack.tag = 0;
     plan.py.tag = plan.py_split.tag = 1;
     plan.pk.tag = plan.upk.tag = 3;
+    tile_passes(plan);
+    return validate_extents(plan);
+}
+
+
+// One task's share of the slab decomposition (Algorithm 3) for p tasks: the
+// spatial slab A[N0/p][N1][N2] and the spectral share X[N0][N1/p][N2c] hold
+// the same number of complex elements, as do the send and receive buffers.
+//   forward  z: in -> out (R2C for R2C plans); y: in place on out, or with
+//            the pack fused, out -> send with element y of line (i0, k2) at
+//            S[y / n1l][i0][y % n1l][k2]; x: recv -> out, the received blocks
+//            stacked along x in sender order (no unpack needed).
+//   inverse  x^-1: in -> send (block r = x rows r n0l ... is contiguous);
+//            y^-1 with the unpack fused, recv -> send, element y of line
+//            (i0, k2) read from R[y / n1l][i0][y % n1l][k2], or unpack then
+//            y^-1 in place on send; z^-1: send -> out (C2R for R2C plans).
+int build_slab(Plan& plan, unsigned /*flags*/)
+{
+    const int P = plan.slab_p;
+    const bool real = plan.kind == MIFFT_R2C;
+    const int N0 = plan.n0, N1 = plan.n1, N2 = plan.n2;
+    const int n0l = N0 / P, n1l = N1 / P, nc = real ? N2 / 2 + 1 : N2;
+    const long long lines = (long long)n0l * N1;
+    const long long blk = (long long)n0l * n1l * nc; // one send block
+    int rc, vx, vy, vz = -1;
+    if ((rc = need_variant(plan, N0, &vx)) || (rc = need_variant(plan, N1, &vy))) return rc;
+    if (!real && (rc = need_variant(plan, N2, &vz))) return rc;
+    // forward
+    if (real)
+        rc = make_real_z(plan, plan.sz, P_R2C, lines);
+    else
+        rc = make_contig(plan, plan.sz, N2, lines, vz);
+    if (rc) return rc;
+    plan.sz.src = B_IN;
+    plan.sz.dst = B_OUT;
+    if ((rc = make_strided(plan, plan.sy, N1, nc, n0l, nc, (long long)N1 * nc, vy, 0))) return rc;
+    plan.sy.src = plan.sy.dst = B_OUT;
+    plan.sy_pack = plan.sy;
+    plan.sy_pack.kind = P_STRIDED_OSPLIT;
+    plan.sy_pack.gs_out = (long long)n1l * nc;
+    plan.sy_pack.es_out = nc;
+    plan.sy_pack.fd = make_fastdiv((uint32_t)n1l);
+    plan.sy_pack.blk = blk;
+    plan.sy_pack.dst = B_SEND;
+    // standalone pack: the pencil pack of [n0l][1][p * (n1l nc)], i.e. the y
+    // axis split into p runs of n1l nc contiguous elements
+    Pass pk;
+    pk.kind = P_PACK;
+    pk.n0 = n0l;
+    pk.n1 = 1;
+    pk.p1 = P;
+    pk.M = n1l * nc;
+    pk.src = B_OUT;
+    pk.dst = B_SEND;
+    plan.spk = pk;
+    if ((rc = make_strided(plan, plan.sx, N0, n1l * nc, 1, (long long)n1l * nc, 0, vx, 0))) return rc;
+    plan.sx.src = B_RECV;
+    plan.sx.dst = B_OUT;
+    plan.sz.sgn = plan.sy.sgn = plan.sy_pack.sgn = plan.sx.sgn = +1;
+    // inverse
+    plan.sxi = plan.sx;
+    plan.sxi.src = B_IN;
+    plan.sxi.dst = B_SEND;
+    Pass up;
+    up.kind = P_UNPACK; // A[i0][s n1l + i1][k2] = R[s][i0][i1][k2]: the pencil unpack
+    up.n0 = n0l;
+    up.n1 = n1l;
+    up.p1 = P;
+    up.M = nc;
+    up.src = B_RECV;
+    up.dst = B_SEND;
+    plan.supk = up;
+    plan.syi = plan.sy;
+    plan.syi.src = plan.syi.dst = B_SEND;
+    plan.syi_unpack = plan.syi;
+    plan.syi_unpack.kind = P_STRIDED_SPLIT;
+    plan.syi_unpack.gs_in = (long long)n1l * nc;
+    plan.syi_unpack.es_in = nc;
+    plan.syi_unpack.fd = make_fastdiv((uint32_t)n1l);
+    plan.syi_unpack.blk = blk;
+    plan.syi_unpack.src = B_RECV;
+    if (real)
+        rc = make_real_z(plan, plan.szi, P_C2R, lines);
+    else
+        rc = make_contig(plan, plan.szi, N2, lines, vz);
+    if (rc) return rc;
+    plan.szi.src = B_SEND;
+    plan.szi.dst = B_OUT;
+    plan.sxi.sgn = plan.syi.sgn = plan.syi_unpack.sgn = plan.szi.sgn = -1;
+    plan.sz.tag = plan.szi.tag = 0;
+    plan.sy.tag = plan.sy_pack.tag = plan.syi.tag = plan.syi_unpack.tag = 1;
+    plan.sx.tag = plan.sxi.tag = 2;
+    plan.spk.tag = plan.supk.tag = 3;
     tile_passes(plan);
     return validate_extents(plan);
 }

@@ -26,7 +26,8 @@ enum PassKind {
     P_PACK,
     P_UNPACK,
     P_COPY,
-    P_POISSON_X // fused x-forward, Poisson multiply, x-inverse (in place)
+    P_POISSON_X, // fused x-forward, Poisson multiply, x-inverse (in place)
+    P_STRIDED_OSPLIT // strided pass storing through a split (slab pack) map
 };
 
 // Which caller buffer a pass reads or writes; resolved at execute time.
@@ -86,6 +87,12 @@ public:
     std::vector<Pass> fwd, inv, poisson;
     // pencil stages
     Pass pz, pz_pack, pk, upk, py, py_split;
+    // slab stages (Algorithm 3) of one of slab_p tasks: forward z, y, y with
+    // the pack fused, standalone pack, x; inverse x, standalone unpack, y,
+    // y with the unpack fused, z
+    bool slab = false;
+    int slab_p = 1;
+    Pass sz, sy, sy_pack, spk, sx, sxi, supk, syi, syi_unpack, szi;
     std::map<int, void*> twiddles; // length -> device table
     void* ws = nullptr;
     size_t ws_bytes = 0;         // workspace an execute call needs
@@ -148,5 +155,6 @@ int build_plan(Plan& plan, unsigned flags);
 void rebuild_poisson(Plan& plan); // re-derive the Poisson pass list from fwd / inv
 void apply_chunking(Plan& plan);  // interleave z/y (x^-1/z^-1) over plane chunks
 int build_pencil(Plan& plan, unsigned flags);
+int build_slab(Plan& plan, unsigned flags);
 
 } // namespace mifft

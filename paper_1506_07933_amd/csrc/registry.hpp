@@ -23,7 +23,8 @@ template <typename T> struct Variant {
     ContigFn<T> contig;
     ContigFn<T> contig_pack;
     StridedFn<T> strided;
-    StridedFn<T> strided_split;
+    StridedFn<T> strided_split;  // loads through the unpack map
+    StridedFn<T> strided_osplit; // stores through the slab pack map
     RealFn<T> r2c; // line of 2L reals
     RealFn<T> c2r;
     PoissonXFn<T> poisson_x; // fused x-forward, multiply, x-inverse

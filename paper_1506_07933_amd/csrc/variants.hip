@@ -27,8 +27,9 @@ template <int L, int P, int E> constexpr Variant<MIFFT_REAL> make_variant()
     for (int i = 0; i < f.n; ++i) v.radix[i] = f.r[i];
     v.contig = &k_contig<MIFFT_REAL, L, P, TPL, false>;
     v.contig_pack = &k_contig<MIFFT_REAL, L, P, TPL, true>;
-    v.strided = &k_strided<MIFFT_REAL, L, P, TPL, false>;
-    v.strided_split = &k_strided<MIFFT_REAL, L, P, TPL, true>;
+    v.strided = &k_strided<MIFFT_REAL, L, P, TPL, 0>;
+    v.strided_split = &k_strided<MIFFT_REAL, L, P, TPL, 1>;
+    v.strided_osplit = &k_strided<MIFFT_REAL, L, P, TPL, 2>;
     v.r2c = &k_r2c_z<MIFFT_REAL, L, P, TPL>;
     v.c2r = &k_c2r_z<MIFFT_REAL, L, P, TPL>;
     v.poisson_x = &k_strided_poisson<MIFFT_REAL, L, P, TPL>;

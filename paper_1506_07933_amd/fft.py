@@ -3,8 +3,8 @@
 torch provides device memory and streams only; every transform step runs in
 libmifft.so.  Names follow the C ABI: ``plan_create``, ``execute_forward``,
 ``execute_inverse``, ``plan_destroy`` and friends take and return raw handles
-and device pointers; ``Plan``, ``PencilPlan`` and ``BatchPlan`` wrap them for
-tensors.
+and device pointers; ``Plan``, ``PencilPlan``, ``SlabPlan`` and ``BatchPlan``
+wrap them for tensors.
 """
 from __future__ import annotations
 
@@ -14,8 +14,9 @@ from typing import Optional, Sequence
 import torch
 
 from ._lib import (MIFFT_C2C, MIFFT_FP32, MIFFT_FP64, MIFFT_HEURISTIC, MIFFT_R2C,
-                   MIFFT_STAGE_PACK, MIFFT_STAGE_UNPACK, MIFFT_STAGE_Y, MIFFT_STAGE_Z,
-                   MIFFT_TUNE, MifftError, check, lib)
+                   MIFFT_SLAB_INVERSE, MIFFT_SLAB_PACK, MIFFT_SLAB_UNPACK, MIFFT_SLAB_X,
+                   MIFFT_SLAB_Y, MIFFT_SLAB_Z, MIFFT_STAGE_PACK, MIFFT_STAGE_UNPACK,
+                   MIFFT_STAGE_Y, MIFFT_STAGE_Z, MIFFT_TUNE, MifftError, check, lib)
 
 _KIND = {"c2c": MIFFT_C2C, "r2c": MIFFT_R2C}
 _PREC = {"fp32": MIFFT_FP32, "fp64": MIFFT_FP64}
@@ -58,6 +59,13 @@ def plan_create_pencil(n0, n1, n2, p0, p1, kind=MIFFT_C2C, prec=MIFFT_FP32, flag
     return h.value
 
 
+def plan_create_slab(n0, n1, n2, p, kind=MIFFT_C2C, prec=MIFFT_FP32, flags=0) -> int:
+    h = ctypes.c_void_p()
+    check(lib.mifft_plan_create_slab(ctypes.byref(h), n0, n1, n2, p, kind, prec, flags),
+          "mifft_plan_create_slab")
+    return h.value
+
+
 def execute_forward(plan: int, in_ptr: int, out_ptr: int, stream: Optional[int] = None) -> None:
     check(lib.mifft_execute_forward(plan, in_ptr, out_ptr, stream), "mifft_execute_forward")
 
@@ -79,6 +87,11 @@ def execute_inverse_ws(plan, in_ptr, out_ptr, ws_ptr, stream=None) -> None:
 def execute_pencil_stages(plan, mask, a, send, recv, out, stream=None) -> None:
     check(lib.mifft_execute_pencil_stages(plan, mask, a, send, recv, out, stream),
           "mifft_execute_pencil_stages")
+
+
+def execute_slab_stages(plan, mask, in_ptr, send, recv, out, stream=None) -> None:
+    check(lib.mifft_execute_slab_stages(plan, mask, in_ptr, send, recv, out, stream),
+          "mifft_execute_slab_stages")
 
 
 def poisson_solve(plan, f_ptr, u_ptr, ws_ptr=None, stream=None) -> None:
@@ -256,7 +269,96 @@ class PencilPlan:
             pass
 
 
-__all__ = ["Plan", "PencilPlan", "MifftError", "plan_create", "plan_create_pencil",
-           "execute_forward", "execute_inverse", "execute_forward_ws", "execute_inverse_ws",
-           "execute_pencil_stages", "poisson_solve", "workspace_bytes", "poisson_ws_bytes",
-           "plan_destroy", "plan_describe", "profile_begin", "profile_end", "version"]
+class SlabPlan:
+    """One task's share of the slab-decomposed transform (Algorithm 3) of an
+    (N0, N1, N2) grid over p tasks: spatial slab (N0/p, N1, N2), spectral
+    share (N0, N1/p, N2c); send / receive buffers (p, N0/p, N1/p, N2c)."""
+
+    def __init__(self, shape: Sequence[int], p: int, kind: str = "c2c", prec: str = "fp32"):
+        self.shape = tuple(int(s) for s in shape)
+        self.p, self.kind, self.prec = int(p), kind, prec
+        self.handle = plan_create_slab(*self.shape, self.p, _KIND[kind], _PREC[prec])
+        n0, n1, n2 = self.shape
+        nc = n2 // 2 + 1 if kind == "r2c" else n2
+        self.n0l, self.n1l, self.nc = n0 // self.p, n1 // self.p, nc
+        self.slab_shape = (self.n0l, n1, n2)
+        self.mid_shape = (self.n0l, n1, nc)      # the 2-D transformed slab
+        self.share_shape = (n0, self.n1l, nc)
+        self.send_shape = (self.p, self.n0l, self.n1l, nc)
+        self.cdtype = _CDTYPE[prec]
+        self.sdtype = _RDTYPE[prec] if kind == "r2c" else self.cdtype
+
+    def stages(self, mask: int, src=None, send=None, recv=None, out=None, stream=None) -> None:
+        """Raw stage call: the tensors are passed as pointers, unchecked."""
+        execute_slab_stages(self.handle, mask, _ptr(src), _ptr(send), _ptr(recv), _ptr(out),
+                            _stream_handle(stream))
+
+    def _check(self, t: torch.Tensor, shape, dtype, name: str):
+        if tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+            raise ValueError("%s must be %s %s, got %s %s" % (name, tuple(shape), dtype,
+                                                               tuple(t.shape), t.dtype))
+
+    def forward_local(self, a: torch.Tensor, send: torch.Tensor, mid: torch.Tensor,
+                      fused: bool = True, stream=None) -> torch.Tensor:
+        """2-D FFTs of the slab's x-planes, written in the send layout; `mid`
+        (mid_shape, complex) holds the z-transformed slab in between."""
+        self._check(a, self.slab_shape, self.sdtype, "slab")
+        self._check(send, self.send_shape, self.cdtype, "send")
+        self._check(mid, self.mid_shape, self.cdtype, "mid")
+        if fused:
+            self.stages(MIFFT_SLAB_Z | MIFFT_SLAB_Y | MIFFT_SLAB_PACK, src=a, send=send, out=mid,
+                        stream=stream)
+        else:
+            self.stages(MIFFT_SLAB_Z | MIFFT_SLAB_Y, src=a, out=mid, stream=stream)
+            self.stages(MIFFT_SLAB_PACK, send=send, out=mid, stream=stream)
+        return send
+
+    def forward_x(self, recv: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """x-FFT of the received slab: out is the spectral share."""
+        self._check(recv, self.send_shape, self.cdtype, "recv")
+        self._check(out, self.share_shape, self.cdtype, "out")
+        self.stages(MIFFT_SLAB_X, recv=recv, out=out, stream=stream)
+        return out
+
+    def inverse_x(self, y: torch.Tensor, send: torch.Tensor, stream=None) -> torch.Tensor:
+        self._check(y, self.share_shape, self.cdtype, "share")
+        self._check(send, self.send_shape, self.cdtype, "send")
+        self.stages(MIFFT_SLAB_INVERSE | MIFFT_SLAB_X, src=y, send=send, stream=stream)
+        return send
+
+    def inverse_local(self, recv: torch.Tensor, send: torch.Tensor, out: torch.Tensor,
+                      fused: bool = True, stream=None) -> torch.Tensor:
+        """Unpack, y-IFFT and z-IFFT (C2R) into the spatial slab `out`; `send`
+        is the complex scratch in between."""
+        self._check(recv, self.send_shape, self.cdtype, "recv")
+        self._check(send, self.send_shape, self.cdtype, "send")
+        self._check(out, self.slab_shape, self.sdtype, "out")
+        if fused:
+            self.stages(MIFFT_SLAB_INVERSE | MIFFT_SLAB_UNPACK | MIFFT_SLAB_Y | MIFFT_SLAB_Z,
+                        recv=recv, send=send, out=out, stream=stream)
+        else:
+            self.stages(MIFFT_SLAB_INVERSE | MIFFT_SLAB_UNPACK, recv=recv, send=send, stream=stream)
+            self.stages(MIFFT_SLAB_INVERSE | MIFFT_SLAB_Y | MIFFT_SLAB_Z, send=send, out=out,
+                        stream=stream)
+        return out
+
+    def describe(self) -> str:
+        return plan_describe(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["Plan", "PencilPlan", "SlabPlan", "MifftError", "plan_create", "plan_create_pencil",
+           "plan_create_slab", "execute_forward", "execute_inverse", "execute_forward_ws",
+           "execute_inverse_ws", "execute_pencil_stages", "execute_slab_stages", "poisson_solve",
+           "workspace_bytes", "poisson_ws_bytes", "plan_destroy", "plan_describe",
+           "profile_begin", "profile_end", "version"]

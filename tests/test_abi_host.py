@@ -28,7 +28,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("mifft_plan_create", "mifft_execute_forward", "mifft_execute_inverse",
                  "mifft_plan_destroy", "mifft_last_error", "mifft_plan_create_pencil",
-                 "mifft_execute_pencil_stages", "mifft_batch_create",
+                 "mifft_execute_pencil_stages", "mifft_plan_create_slab",
+                 "mifft_execute_slab_stages", "mifft_batch_create",
                  "mifft_batch_execute_forward", "mifft_poisson_solve"):
         assert must in names
 
@@ -83,6 +84,27 @@ def test_pencil_validation(L):
     assert f(None, 1024, 1024, 1024, 4, 4, 0, 0, 0) == 1
 
 
+def test_slab_validation(L):
+    h = ctypes.c_void_p()
+    f = L.mifft_plan_create_slab
+    assert f(ctypes.byref(h), 512, 512, 512, 3, 0, 0, 0) == 2     # 3 does not divide 512
+    assert f(ctypes.byref(h), 512, 96, 512, 64, 0, 0, 0) == 2     # p divides N0 but not N1
+    assert f(ctypes.byref(h), 512, 512, 512, 0, 0, 0, 0) == 1
+    assert f(ctypes.byref(h), 512, 512, 511, 4, 1, 0, 0) == 2     # R2C needs an even n2
+    assert f(ctypes.byref(h), 512, 512, 512, 4, 0, 0, 1) == 1     # MIFFT_TUNE not offered
+    assert f(ctypes.byref(h), 512, 512, 512, 4, 3, 0, 0) == 1     # bad kind
+    assert f(None, 512, 512, 512, 4, 0, 0, 0) == 1
+    # a plan-only slab plan describes but never executes
+    assert f(ctypes.byref(h), 64, 32, 16, 4, 1, 1, 2) == 0
+    buf = ctypes.c_void_p(0x10000)
+    assert L.mifft_execute_slab_stages(h, 1, buf, buf, buf, buf, None) == 5
+    assert L.mifft_execute_forward(h, buf, buf, None) == 5
+    assert b"slab" in L.mifft_last_error()
+    assert L.mifft_execute_pencil_stages(h, 1, buf, buf, buf, buf, None) == 5
+    assert L.mifft_workspace_bytes(h) == 0
+    assert L.mifft_plan_destroy(h) == 0
+
+
 def test_stale_and_null_handles(L):
     bogus = ctypes.c_void_p(0x1234560)
     assert L.mifft_plan_destroy(None) == 0
@@ -92,6 +114,8 @@ def test_stale_and_null_handles(L):
     assert L.mifft_execute_forward(bogus, buf, buf, None) == 5
     assert L.mifft_execute_inverse(bogus, buf, buf, None) == 5
     assert L.mifft_execute_pencil_stages(bogus, 1, buf, buf, buf, buf, None) == 5
+    assert L.mifft_execute_slab_stages(bogus, 1, buf, buf, buf, buf, None) == 5
+    assert L.mifft_execute_slab_stages(None, 1, buf, buf, buf, buf, None) == 1
     assert L.mifft_poisson_solve(bogus, buf, buf, None, None) == 5
     assert L.mifft_workspace_bytes(bogus) == 0
     s = ctypes.create_string_buffer(64)
@@ -126,6 +150,7 @@ def test_package_exports_load_the_library():
     import paper_1506_07933_amd as pkg
     assert pkg.Plan.__name__ == "Plan"
     assert pkg.PencilPlan.__name__ == "PencilPlan"
+    assert pkg.SlabPlan.__name__ == "SlabPlan"
     assert issubclass(pkg.MifftError, RuntimeError)
     from paper_1506_07933_amd import Plan  # noqa: F401
 

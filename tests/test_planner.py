@@ -229,3 +229,61 @@ def test_pencil_passes_stay_inside_the_share(shape, grid):
         rc = lib.mifft_plan_create_pencil(ctypes.byref(h), *shape, *grid, 0, prec, MIFFT_PLAN_ONLY)
         assert rc == 0, lib.mifft_last_error()
         plan_destroy(h.value)
+
+
+def slab_only(shape, p, kind=0, prec=0):
+    h = ctypes.c_void_p()
+    rc = lib.mifft_plan_create_slab(ctypes.byref(h), *shape, p, kind, prec, MIFFT_PLAN_ONLY)
+    assert rc == 0, lib.mifft_last_error()
+    text = plan_describe(h.value)
+    plan_destroy(h.value)
+    out = {}
+    for line in text.splitlines():
+        d = dict(kv.split("=") for kv in line.split()[1:])
+        out[line.split()[0]] = d
+    return out
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_slab_plan_stages(kind):
+    """Slab share of 512^3 over 4 tasks (Algorithm 3): z over the slab's
+    (N0/p) N1 lines, y over (N0/p) groups of N2c columns with the pack fused
+    into its stores (split every N1/p rows into blocks of (N0/p)(N1/p)N2c),
+    x over the received slab (one group of (N1/p) N2c columns), and the
+    inverse's y with the unpack fused into its loads."""
+    n, p = 512, 4
+    nc = n // 2 + 1 if kind else n
+    st = slab_only((n, n, n), p, kind)
+    z = st["slab_z"]
+    assert z["kind"] == ("r2c_z" if kind else "contig")
+    assert int(z["lines"]) == (n // p) * n
+    y, yp = st["slab_y"], st["slab_y_pack"]
+    assert (y["kind"], yp["kind"]) == ("strided", "strided_pack")
+    assert ints(yp, "L", "cols", "groups") == [n, nc, n // p]
+    assert yp["es"] == "%d/%d" % (nc, nc)
+    assert yp["gs"] == "%d/%d" % (n * nc, (n // p) * nc)
+    x = st["slab_x"]
+    assert ints(x, "L", "cols", "groups") == [n, (n // p) * nc, 1]
+    assert x["es"] == "%d/%d" % ((n // p) * nc, (n // p) * nc)
+    assert st["slab_x_inv"]["sgn"] == "-1"
+    yu = st["slab_unpack_y_inv"]
+    assert yu["kind"] == "strided_unpack" and yu["sgn"] == "-1"
+    assert yu["gs"] == "%d/%d" % ((n // p) * nc, n * nc)
+    assert st["slab_z_inv"]["kind"] == ("c2r_z" if kind else "contig")
+    assert st["slab_pack"]["kind"] == "pack" and st["slab_unpack"]["kind"] == "unpack"
+
+
+@pytest.mark.parametrize("shape,p", [((512, 512, 512), 4), ((512, 512, 512), 512), ((64, 96, 120), 2),
+                                     ((125, 125, 120), 5), ((8, 8, 2), 8), ((4, 6, 1), 2),
+                                     ((1, 1, 1), 1), ((1024, 1024, 32), 64)])
+def test_slab_passes_stay_inside_the_share(shape, p):
+    """Every slab stage's reads and writes stay inside the share's buffers
+    (checked by the library at plan time, for both kinds and precisions)."""
+    for kind in (0, 1):
+        if kind == 1 and shape[2] % 2:
+            continue
+        for prec in (0, 1):
+            h = ctypes.c_void_p()
+            rc = lib.mifft_plan_create_slab(ctypes.byref(h), *shape, p, kind, prec, MIFFT_PLAN_ONLY)
+            assert rc == 0, (shape, p, kind, prec, lib.mifft_last_error())
+            plan_destroy(h.value)
