@@ -82,10 +82,42 @@ def copy_mode(args):
                       "ms": ms, "GBps": 16 * n / ms / 1e6}), flush=True)
 
 
+def slab_share(torch, np, time_fn, warmup, steps):
+    """One task's share of the 512^3 C2C FP32 slab transform over 4 tasks
+    (Algorithm 3): the 2-D FFTs of its 128 x-planes written in the send
+    layout, and the x-FFT of a received 512 x 128 x 512 slab (the send buffer
+    stands in for the receive buffer: one GPU moves no blocks); then the
+    inverse stages.  Algorithmic bytes: one read and one write of the share
+    per axis pass."""
+    from paper_1506_07933_amd import SlabPlan, synth
+    sp = SlabPlan((512, 512, 512), 4, "c2c", "fp32")
+    cd = torch.complex64
+    a = torch.from_numpy(synth.uniform_complex(sp.slab_shape, np.complex64, seed=0)).cuda()
+    send = torch.empty(sp.send_shape, dtype=cd, device="cuda")
+    recv = torch.empty(sp.send_shape, dtype=cd, device="cuda")
+    mid = torch.empty(sp.mid_shape, dtype=cd, device="cuda")
+    sh = torch.empty(sp.share_shape, dtype=cd, device="cuda")
+    back = torch.empty(sp.slab_shape, dtype=cd, device="cuda")
+    ns = a.numel()
+    loc = time_fn(lambda: sp.forward_local(a, send, mid, fused=True), warmup, steps)
+    xf = time_fn(lambda: sp.forward_x(send, sh), warmup, steps)
+    unf = time_fn(lambda: sp.forward_local(a, send, mid, fused=False), warmup, max(3, steps // 4))
+    recv.copy_(send)
+    xi = time_fn(lambda: sp.inverse_x(sh, send), warmup, steps)
+    li = time_fn(lambda: sp.inverse_local(recv, send, back, fused=True), warmup, steps)
+    sp.close()
+    fwd = loc + xf
+    return {"forward_local_2d_ms": round(loc, 4), "forward_x_ms": round(xf, 4), "forward_ms": round(fwd, 4),
+            "forward_alg_GBps": round(48 * ns / fwd / 1e6, 1),
+            "forward_local_unfused_ms": round(unf, 4),
+            "inverse_x_ms": round(xi, 4), "inverse_local_2d_ms": round(li, 4),
+            "inverse_alg_GBps": round(48 * ns / (xi + li) / 1e6, 1)}
+
+
 def workload_mode(args):
     """One secondary workload alone (for rocprofv3): the 64 uneven transforms
-    in one persistent graph launch and as per-pass kernels, or 512^3 R2C
-    Poisson solves (FP32 and FP64)."""
+    in one persistent graph launch and as per-pass kernels, 512^3 R2C
+    Poisson solves (FP32 and FP64), or one task's 512^3 slab share."""
     import numpy as np
     import torch
 
@@ -103,6 +135,8 @@ def workload_mode(args):
         out["per_pass_kernels_ms"] = time_fn(lambda: bk.forward(xs, outs), args.warmup, args.steps)
         bp.close()
         bk.close()
+    elif args.mode == "slab":
+        out.update(slab_share(torch, np, time_fn, args.warmup, args.steps))
     else:
         for prec, dt in (("fp32", np.float32), ("fp64", np.float64)):
             f, _ = synth.poisson_rhs(512, seed=0, dtype=dt)
@@ -171,6 +205,7 @@ def secondary(torch, np, steps):
         "unfused_ms_incl_input_copy": round(unfused, 4)}
     pp.close()
     del a, send, ob
+    out["slab_share_512cube_p4_fp32"] = slab_share(torch, np, time_fn, 2, steps)
     # 64 uneven transforms in one persistent graph launch vs per-pass kernels
     shapes, data = synth.batched_uneven(64, seed=0, dtype=np.complex64)
     xs = [torch.from_numpy(d).cuda() for d in data]
@@ -200,9 +235,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson"], default="fft",
-                    help="copy: plain 1 GiB device copy (counter scaling); batched / poisson: only "
-                         "that secondary workload, for profiling")
+    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab"], default="fft",
+                    help="copy: plain 1 GiB device copy (counter scaling); batched / poisson / "
+                         "slab: only that secondary workload, for profiling")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -211,7 +246,7 @@ def main():
         sys.exit(2)
     if args.mode == "copy":
         return copy_mode(args)
-    if args.mode in ("batched", "poisson"):
+    if args.mode in ("batched", "poisson", "slab"):
         return workload_mode(args)
 
     import numpy as np
