@@ -17,6 +17,8 @@ Contents
   * ``slab_pack / slab_forward / slab_inverse`` -- the slab decomposition of
     Algorithm 3 for all tasks at once, the all-to-all done as array copies;
     ``c2r_z`` is the z-only C2R its inverse ends with.
+  * ``fftnd_c2c / fftnd_r2c / fftnd_c2r`` -- transforms of any rank in the
+    axis order of Algorithm 2 (last axis first; the inverse first axis first).
   * ``brute`` submodule -- the direct O(N^2) DFT used to pin the FFT.
 
 Conventions (readings of the paper, listed in the design notes): forward uses
@@ -274,3 +276,36 @@ def slab_inverse(shares, p: int, n2: int = None) -> list:
         a = fft_axis(a, 1, +1)
         slabs.append(c2r_z(a, n2) if n2 is not None else fft_axis(a, 2, +1))
     return slabs
+
+
+# ---- arrays of any rank (Algorithm 2 with every P_i = 1) ----
+
+def fftnd_c2c(x, sign: int = -1) -> np.ndarray:
+    """Unscaled N-D DFT: 1-D DFTs along the last axis, then along each earlier
+    axis in turn (the forward loop of Algorithm 2); the inverse (sign = +1)
+    runs the axes first to last, as Algorithm 2's inverse does."""
+    a = _as_c128(x)
+    order = range(a.ndim - 1, -1, -1) if sign < 0 else range(a.ndim)
+    for ax in order:
+        a = fft_axis(a, ax, sign)
+    return a
+
+
+def fftnd_r2c(x) -> np.ndarray:
+    """Real N-D array -> half spectrum (last axis n//2 + 1), unscaled."""
+    a = np.asarray(x, dtype=np.float64)
+    n = a.shape[-1]
+    a = fft_axis(a, a.ndim - 1, -1)[..., :n // 2 + 1]
+    for ax in range(a.ndim - 2, -1, -1):
+        a = fft_axis(a, ax, -1)
+    return a
+
+
+def fftnd_c2r(y, n_last: int) -> np.ndarray:
+    """Half spectrum -> real N-D array, unscaled: inverse DFTs along the first
+    axes in order, then the C2R of the last axis (imaginary parts at k = 0
+    and n/2 discarded)."""
+    a = _as_c128(y)
+    for ax in range(a.ndim - 1):
+        a = fft_axis(a, ax, +1)
+    return c2r_z(a, n_last)

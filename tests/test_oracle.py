@@ -14,6 +14,9 @@ Each pin is chosen so a plausible mistake fails at least one test:
   * the pencil pack / exchange / unpack maps against a textbook 2-D DFT
   * the slab decomposition (Algorithm 3) for all tasks against the brute
     force 3-D DFT, its inverse against the C2R cosine sum and N x
+  * transforms of any rank against a direct N-D DFT sum over all index
+    pairs, numpy.fft.fftn / rfftn / irfftn, and the 3-D oracle for a
+    leading extent of 1
 """
 import os
 
@@ -365,6 +368,41 @@ def test_c2r_z_lines():
         if n2 % 2 == 0:
             bent[..., n2 // 2] -= 2j
         np.testing.assert_array_equal(oracle.c2r_z(bent, n2), oracle.c2r_z(half, n2))
+
+
+# ------------------------------------------------------------ any rank
+
+def _direct_dft_nd(x, sign):
+    """X[k] = sum_a x[a] exp(sign 2 pi i sum_j k_j a_j / n_j), every (k, a) pair
+    at once: one dense matrix over all flattened index pairs (tiny arrays)."""
+    shape = x.shape
+    idx = np.stack(np.unravel_index(np.arange(x.size), shape), axis=1).astype(np.float64)
+    frac = idx / np.asarray(shape, dtype=np.float64)
+    phase = (idx @ frac.T) % 1.0           # sum_j k_j a_j / n_j for every (k, a)
+    return (np.exp(sign * 2j * np.pi * phase) @ x.ravel()).reshape(shape)
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 4, 5), (4, 1, 6, 2), (3, 2, 2, 2, 3), (5,), (6, 10),
+                                   (1, 1, 1, 1), (2, 2, 3, 1, 2, 2)])
+@pytest.mark.parametrize("sign", [-1, +1])
+def test_fftnd_direct_sum(shape, sign):
+    x = _rand_c(shape, 26)
+    assert rel_l2(oracle.fftnd_c2c(x, sign), _direct_dft_nd(x, sign)) < 1e-13
+
+
+def test_fftnd_matches_numpy_and_3d():
+    x = _rand_c((4, 6, 10, 8), 27)
+    assert rel_l2(oracle.fftnd_c2c(x, -1), np.fft.fftn(x)) < 1e-13
+    assert rel_l2(oracle.fftnd_c2c(x, +1), x.size * np.fft.ifftn(x)) < 1e-13
+    y = _rand_c((1, 6, 10, 8), 28)
+    assert rel_l2(oracle.fftnd_c2c(y, -1)[0], oracle.fft3d_c2c(y[0], -1)) < 1e-13
+    rng = np.random.default_rng(29)
+    r = rng.standard_normal((3, 5, 4, 6))
+    assert rel_l2(oracle.fftnd_r2c(r), np.fft.rfftn(r)) < 1e-13
+    h = _rand_c((3, 5, 4, 4), 30)      # not Hermitian: numpy drops the same parts
+    n = 3 * 5 * 4 * 6
+    assert rel_l2(oracle.fftnd_c2r(h, 6), n * np.fft.irfftn(h, s=(3, 5, 4, 6), axes=(0, 1, 2, 3))) < 1e-13
+    assert rel_l2(oracle.fftnd_c2r(oracle.fftnd_r2c(r), 6), r.size * r) < 1e-13
 
 
 def test_fft_axis_matches_numpy():
