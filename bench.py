@@ -114,10 +114,32 @@ def slab_share(torch, np, time_fn, warmup, steps):
             "inverse_alg_GBps": round(48 * ns / (xi + li) / 1e6, 1)}
 
 
+def nd_4d(torch, time_fn, warmup, steps):
+    """The paper's 4-D C2C case, 512 x 256 x 128 x 64 complex64 (8 GiB), one
+    forward and one inverse (in place) through the rank-4 plan; input
+    U[-1,1) from torch's device generator seeded with 0.  Algorithmic bytes:
+    one read and one write per axis pass, 4 x 16 bytes per element."""
+    from paper_1506_07933_amd import Plan
+    shape = (512, 256, 128, 64)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    x = torch.complex(torch.rand(shape, device="cuda", generator=g) * 2 - 1,
+                      torch.rand(shape, device="cuda", generator=g) * 2 - 1)
+    y = torch.empty_like(x)
+    p = Plan(shape, "c2c", "fp32")
+    f = time_fn(lambda: p.forward(x, out=y), warmup, steps)
+    i = time_fn(lambda: p.inverse(y, out=y), warmup, steps)
+    p.close()
+    n = x.numel()
+    return {"forward_ms": round(f, 4), "forward_alg_GBps": round(64 * n / f / 1e6, 1),
+            "inverse_in_place_ms": round(i, 4), "inverse_alg_GBps": round(64 * n / i / 1e6, 1)}
+
+
 def workload_mode(args):
     """One secondary workload alone (for rocprofv3): the 64 uneven transforms
     in one persistent graph launch and as per-pass kernels, 512^3 R2C
-    Poisson solves (FP32 and FP64), or one task's 512^3 slab share."""
+    Poisson solves (FP32 and FP64), one task's 512^3 slab share, or the 4-D
+    512 x 256 x 128 x 64 C2C transform."""
     import numpy as np
     import torch
 
@@ -137,6 +159,8 @@ def workload_mode(args):
         bk.close()
     elif args.mode == "slab":
         out.update(slab_share(torch, np, time_fn, args.warmup, args.steps))
+    elif args.mode == "nd":
+        out.update(nd_4d(torch, time_fn, args.warmup, args.steps))
     else:
         for prec, dt in (("fp32", np.float32), ("fp64", np.float64)):
             f, _ = synth.poisson_rhs(512, seed=0, dtype=dt)
@@ -206,6 +230,7 @@ def secondary(torch, np, steps):
     pp.close()
     del a, send, ob
     out["slab_share_512cube_p4_fp32"] = slab_share(torch, np, time_fn, 2, steps)
+    out["c2c_4d_512x256x128x64_fp32"] = nd_4d(torch, time_fn, 2, max(3, steps // 4))
     # 64 uneven transforms in one persistent graph launch vs per-pass kernels
     shapes, data = synth.batched_uneven(64, seed=0, dtype=np.complex64)
     xs = [torch.from_numpy(d).cuda() for d in data]
@@ -235,9 +260,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab"], default="fft",
+    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab", "nd"], default="fft",
                     help="copy: plain 1 GiB device copy (counter scaling); batched / poisson / "
-                         "slab: only that secondary workload, for profiling")
+                         "slab / nd: only that secondary workload, for profiling")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -246,7 +271,7 @@ def main():
         sys.exit(2)
     if args.mode == "copy":
         return copy_mode(args)
-    if args.mode in ("batched", "poisson", "slab"):
+    if args.mode in ("batched", "poisson", "slab", "nd"):
         return workload_mode(args)
 
     import numpy as np

@@ -152,6 +152,23 @@ int mifft_plan_destroy(mifft_plan plan);
 const char* mifft_last_error(void);
 
 /*
+ * mifft_plan_create_nd -- plan a transform of a C-order array of any rank
+ * 1 .. MIFFT_MAX_RANK (Algorithm 2 with one task per axis: batched 1-D FFTs
+ * along the last axis, then along each earlier axis in turn; the inverse in
+ * the opposite order).  dims[0] is the slowest extent, dims[rank-1] the
+ * contiguous one; R2C halves the last axis to dims[rank-1]/2 + 1.  Rank 1 .. 3
+ * is the 3-D plan of mifft_plan_create with leading extents of 1 (all its
+ * flags apply); rank >= 4 takes MIFFT_PLAN_ONLY only (MIFFT_TUNE:
+ * UNSUPPORTED) and has at most 2^31 - 1 elements.  Execute with
+ * mifft_execute_forward / _inverse (and the _ws variants); the C2R inverse
+ * keeps its input (its complex passes run in the workspace).  The Poisson
+ * solve needs a rank-3 plan.  Errors as mifft_plan_create, plus INVALID for
+ * a NULL dims or a rank outside 1 .. MIFFT_MAX_RANK.
+ */
+#define MIFFT_MAX_RANK 8
+int mifft_plan_create_nd(mifft_plan* out, int rank, const int* dims, int kind, int prec, unsigned flags);
+
+/*
  * mifft_plan_create_pencil -- plan one rank's share of the pencil-decomposed
  * forward transform of an N0 x N1 x N2 C2C grid on a p0 x p1 process grid
  * (Sec. 2, pencil paragraph; Algorithm 1, steps 1-3).  The share is the

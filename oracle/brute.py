@@ -1,4 +1,5 @@
-"""Direct O(N^2) 3-D DFT: the definition, summed term by term.
+"""Direct O(N^2) 3-D DFT: the definition, summed term by term (and the N-D
+definition at sampled outputs, ``dftnd_at``).
 
 TEST INFRASTRUCTURE ONLY (pins the oracle; see the package docstring).
 
@@ -64,4 +65,38 @@ def brute_dft3_at(x, ks, sign: int = -1) -> np.ndarray:
     for i, (q0, q1, q2) in enumerate(ks):
         e = (q0 * pa + q1 * pb + q2 * pc) % big_l
         out[i] = np.dot(table[e], xv)
+    return out
+
+
+def dftnd_at(x, ks, sign: int = -1, chunk_rows: int = 1 << 18) -> np.ndarray:
+    """The N-D DFT sum X[k] = sum_a x[a] exp(sign 2 pi i sum_j k_j a_j / n_j)
+    evaluated only at the listed outputs ks (S, rank), for arrays too large
+    for a full transform.  The exponential of the sum is the product of the
+    per-axis exponentials, so the sum is contracted one axis at a time (the
+    last axis for all S outputs at once, over row chunks of the leading
+    axes, in FP64), against phase vectors whose phases are reduced exactly in
+    integers: exp(sign 2 pi i ((k_j a_j) mod n_j) / n_j)."""
+    x = np.asarray(x)
+    shape = x.shape
+    r = x.ndim
+    ks = np.asarray(ks, dtype=np.int64).reshape(-1, r)
+    n_out = len(ks)
+
+    def phase(j, kcol):
+        n = shape[j]
+        e = (np.arange(n, dtype=np.int64)[:, None] * np.asarray(kcol, dtype=np.int64)[None, :]) % n
+        return np.exp(sign * 2j * np.pi * e / n)
+
+    lead = int(np.prod(shape[:-1], dtype=np.int64))
+    flat = x.reshape(lead, shape[-1])
+    w_last = phase(r - 1, ks[:, r - 1])
+    part = np.empty((lead, n_out), dtype=np.complex128)
+    for s in range(0, lead, chunk_rows):
+        part[s:s + chunk_rows] = flat[s:s + chunk_rows].astype(np.complex128) @ w_last
+    out = np.empty(n_out, dtype=np.complex128)
+    for i in range(n_out):
+        v = part[:, i].reshape(shape[:-1])
+        for j in range(r - 2, -1, -1):
+            v = v @ phase(j, [ks[i, j]])[:, 0]
+        out[i] = v
     return out

@@ -36,6 +36,7 @@ SIGNATURES = {
     "mifft_plan_create_pencil": (_i, [_vpp, _i, _i, _i, _i, _i, _i, _i, _u]),
     "mifft_execute_pencil_stages": (_i, [_vp, _u, _vp, _vp, _vp, _vp, _vp]),
     "mifft_plan_create_slab": (_i, [_vpp, _i, _i, _i, _i, _i, _i, _u]),
+    "mifft_plan_create_nd": (_i, [_vpp, _i, ctypes.POINTER(ctypes.c_int), _i, _i, _u]),
     "mifft_execute_slab_stages": (_i, [_vp, _u, _cvp, _vp, _vp, _vp, _vp]),
     "mifft_poisson_ws_bytes": (_sz, [_vp]),
     "mifft_poisson_solve": (_i, [_vp, _cvp, _vp, _vp, _vp]),

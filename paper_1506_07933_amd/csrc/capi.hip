@@ -146,6 +146,79 @@ int mifft_plan_create(mifft_plan* out, int n0, int n1, int n2, int kind, int pre
     return finish_plan(p, out);
 }
 
+int mifft_plan_create_nd(mifft_plan* out, int rank, const int* dims, int kind, int prec, unsigned flags)
+{
+    clear_error();
+    if (!out) return set_error(MIFFT_ERR_INVALID, "out is NULL");
+    if (!dims) return set_error(MIFFT_ERR_INVALID, "dims is NULL");
+    if (rank < 1 || rank > MIFFT_MAX_RANK)
+        return set_error(MIFFT_ERR_INVALID, "rank %d must be 1 .. %d", rank, MIFFT_MAX_RANK);
+    if (rank <= 3) { // leading extents of 1: the 3-D plan
+        int n[3] = {1, 1, 1};
+        for (int i = 0; i < rank; ++i) n[3 - rank + i] = dims[i];
+        return mifft_plan_create(out, n[0], n[1], n[2], kind, prec, flags);
+    }
+    if (kind != MIFFT_C2C && kind != MIFFT_R2C)
+        return set_error(MIFFT_ERR_INVALID, "kind %d is not MIFFT_C2C or MIFFT_R2C", kind);
+    if (prec != MIFFT_FP32 && prec != MIFFT_FP64)
+        return set_error(MIFFT_ERR_INVALID, "precision %d is not MIFFT_FP32 or MIFFT_FP64", prec);
+    long long total = 1;
+    for (int i = 0; i < rank; ++i) {
+        if (dims[i] < 1) return set_error(MIFFT_ERR_INVALID, "dims[%d] = %d must be >= 1", i, dims[i]);
+        total *= dims[i];
+        if (total >= (1LL << 31))
+            return set_error(MIFFT_ERR_UNSUPPORTED, "more than 2^31 - 1 elements");
+    }
+    for (int i = 0; i < rank; ++i)
+        if (!supported_length(dims[i]))
+            return set_error(MIFFT_ERR_UNSUPPORTED,
+                             "dims[%d] = %d: axis lengths must be <= 1024 with prime factors 2, 3, 5", i, dims[i]);
+    if (kind == MIFFT_R2C && dims[rank - 1] % 2)
+        return set_error(MIFFT_ERR_UNSUPPORTED, "R2C needs an even last extent (got %d)", dims[rank - 1]);
+    if (flags & ~(unsigned)(MIFFT_TUNE | MIFFT_PLAN_ONLY))
+        return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if (flags & MIFFT_TUNE) return set_error(MIFFT_ERR_UNSUPPORTED, "MIFFT_TUNE is offered for rank <= 3");
+    int dev = 0, rc;
+    const bool plan_only = flags & MIFFT_PLAN_ONLY;
+    if (!plan_only && (rc = check_device(&dev))) return rc;
+    mifft_plan_s* p = new mifft_plan_s();
+    p->plan_only = plan_only;
+    p->nd = true;
+    p->dims.assign(dims, dims + rank);
+    p->n0 = 1;
+    for (int i = 0; i + 2 < rank; ++i) p->n0 *= dims[i];
+    p->n1 = dims[rank - 2];
+    p->n2 = dims[rank - 1];
+    p->kind = kind;
+    p->prec = prec;
+    p->device = dev;
+    if (!plan_only) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p->cus = cus;
+    }
+    p->esz = prec == MIFFT_FP64 ? 16 : 8;
+    if ((rc = build_nd(*p, flags))) {
+        delete p;
+        return rc;
+    }
+    if (plan_only) {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        g_live.insert(p);
+        *out = static_cast<mifft_plan>(p);
+        return MIFFT_OK;
+    }
+    if (p->default_ws_bytes) {
+        hipError_t e = hipMalloc(&p->ws, p->default_ws_bytes);
+        if (e != hipSuccess) {
+            delete p;
+            return set_error(MIFFT_ERR_NOMEM, "workspace of %zu bytes: %s", p->default_ws_bytes,
+                             hipGetErrorString(e));
+        }
+    }
+    return finish_plan(p, out);
+}
+
 int mifft_plan_create_pencil(mifft_plan* out, int n0, int n1, int n2, int p0, int p1, int kind,
                              int prec, unsigned flags)
 {
@@ -365,8 +438,8 @@ int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void*
     clear_error();
     if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
-    if (plan->pencil || plan->slab || plan->kind != MIFFT_R2C)
-        return set_error(MIFFT_ERR_BADPLAN, "the Poisson solve needs an R2C plan");
+    if (plan->pencil || plan->slab || plan->nd || plan->kind != MIFFT_R2C)
+        return set_error(MIFFT_ERR_BADPLAN, "the Poisson solve needs a 3-D R2C plan");
     if (plan->plan_only) return set_error(MIFFT_ERR_BADPLAN, "plan was built with MIFFT_PLAN_ONLY");
     if (!f || !u) return set_error(MIFFT_ERR_INVALID, "f / u must not be NULL");
     if (!aligned16(f) || !aligned16(u) || (ws && !aligned16(ws)))

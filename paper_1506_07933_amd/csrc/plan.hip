@@ -454,8 +454,16 @@ static int make_contig(Plan& plan, Pass& p, int L, long long nlines, int vidx)
 // Column-tile shape of a strided pass: aim at 256-byte rows (B = 32 complex64
 // or 16 complex128), the widest row that keeps the tile within 128 KiB of LDS
 // and the workgroup within 1024 threads, trying the variants of L with the
-// most threads per line first.
-static void choose_strided(const Plan& plan, int L, int* vidx, int* B)
+// most threads per line first.  A group of more columns than that but at
+// most twice as many (33 .. 64 complex64) is taken whole -- one tile per
+// group, one contiguous block -- where that is not a multiple of the 256-byte
+// row (e.g. the 51 of a half spectrum of 100: a full tile and a nearly empty
+// one otherwise) or where the groups alone fill the device several times
+// over (MIFFT_NARROW_TILES=0 keeps 256-byte rows, for comparison).
+// Measured: R2C 256 x 256 x 100 forward 0.047 -> 0.042 ms; the 64-column
+// axis of 512 x 256 x 128 x 64, 131072 groups: 3.42 -> 3.18 ms; with few
+// groups (64^3) whole tiles were 7% slower.
+static void choose_strided(const Plan& plan, int L, int cols, int groups, int* vidx, int* B)
 {
     const int esz = (int)plan.esz;
     std::vector<int> cands;
@@ -464,6 +472,21 @@ static void choose_strided(const Plan& plan, int L, int* vidx, int* B)
     std::sort(cands.begin(), cands.end(), [&](int a, int b) {
         return variant_tpl(plan.prec, a) > variant_tpl(plan.prec, b);
     });
+    int whole = 1;
+    while (whole < cols) whole *= 2;
+    bool narrow = true;
+    if (const char* e = getenv("MIFFT_NARROW_TILES"))
+        if (atoi(e) == 0) narrow = false;
+    const bool many = (long long)groups >= 8LL * plan.cus;
+    if (narrow && whole > 256 / esz && whole <= 512 / esz && (cols % (256 / esz) != 0 || many))
+        for (int v : cands) {
+            const int tpl = variant_tpl(plan.prec, v);
+            if ((long long)tpl * whole <= 1024 && (size_t)(whole + 1) * L * esz <= 136 * 1024) {
+                *vidx = v;
+                *B = whole;
+                return;
+            }
+        }
     for (int b = 256 / esz; b >= 1; b /= 2)
         for (int v : cands) {
             const int tpl = variant_tpl(plan.prec, v);
@@ -480,7 +503,7 @@ static void choose_strided(const Plan& plan, int L, int* vidx, int* B)
 static int make_strided(Plan& plan, Pass& p, int L, int cols, int groups, long long es,
                         long long gs, int vidx, int forceB)
 {
-    if (forceB == 0) choose_strided(plan, L, &vidx, &forceB);
+    if (forceB == 0) choose_strided(plan, L, cols, groups, &vidx, &forceB);
     p.kind = P_STRIDED;
     p.vidx = vidx;
     int rc = get_twiddles(plan, L, (void**)&p.tw);
@@ -1204,6 +1227,133 @@ int build_slab(Plan& plan, unsigned /*flags*/)
     plan.sy.tag = plan.sy_pack.tag = plan.syi.tag = plan.syi_unpack.tag = 1;
     plan.sx.tag = plan.sxi.tag = 2;
     plan.spk.tag = plan.supk.tag = 3;
+    tile_passes(plan);
+    return validate_extents(plan);
+}
+
+
+// Arrays of rank d + 1 > 3 in C order (Algorithm 2 with every P_i = 1): the
+// forward runs 1-D FFTs along the last axis (contiguous lines; R2C for real
+// plans), then along axes d - 1, ..., 0, each a strided pass whose columns
+// are the elements after the axis and whose groups are the index ranges
+// before it; the inverse runs axes 0, ..., d - 1 and then the last axis
+// (C2R for real plans).  Axes of length 1 are skipped.
+//
+// With a large stride of axis 0 (the rows of a column tile each in a
+// different translation page) the 3-D plan's transposed intermediate is
+// used with the axes after axis 1 flattened into one: the axis-1 pass
+// writes W[k1][x0][rest] into the workspace and the axis-0 pass reads W with
+// stride `rest` and writes the standard layout; the inverse runs axis 1
+// (input -> W), axis 0 (W -> standard layout), then the others.  The C2R
+// keeps its input, so a real plan's inverse runs its complex passes in the
+// workspace (two spectra when W is used).
+int build_nd(Plan& plan, unsigned /*flags*/)
+{
+    const std::vector<int>& d = plan.dims;
+    const int r = (int)d.size();
+    const bool real = plan.kind == MIFFT_R2C;
+    const int nl = d[r - 1];
+    const long long nc = real ? nl / 2 + 1 : nl;
+    std::vector<long long> inner(r), outer(r);
+    inner[r - 1] = 1;
+    for (int i = r - 2; i >= 0; --i) inner[i] = inner[i + 1] * (i + 1 == r - 1 ? nc : d[i + 1]);
+    outer[0] = 1;
+    for (int i = 1; i < r; ++i) outer[i] = outer[i - 1] * d[i - 1];
+    const long long lines = outer[r - 1];
+    const size_t spec_bytes = (size_t)lines * (size_t)nc * plan.esz;
+    const long long rest = inner[1];
+    const bool T = d[0] > 1 && d[1] > 1 && (size_t)d[1] * rest * plan.esz >= (size_t)256 * 1024;
+    plan.transposed = false; // the 3-D line maps of W do not apply
+    int rc, vz = -1;
+    if (!real && nl > 1 && (rc = need_variant(plan, nl, &vz))) return rc;
+    // one strided pass per axis before the last, standard layout, indexed by axis
+    std::vector<Pass> ax(r);
+    std::vector<bool> has(r, false);
+    for (int i = r - 2; i >= 0; --i) {
+        if (d[i] == 1) continue;
+        int v;
+        if ((rc = need_variant(plan, d[i], &v))) return rc;
+        if (inner[i] >= (1LL << 31) || outer[i] >= (1LL << 31))
+            return set_error(MIFFT_ERR_UNSUPPORTED, "axis %d: %lld columns x %lld groups is too large", i,
+                             inner[i], outer[i]);
+        if ((rc = make_strided(plan, ax[i], d[i], (int)inner[i], (int)outer[i], inner[i], d[i] * inner[i], v, 0)))
+            return rc;
+        ax[i].tag = i == r - 2 ? 1 : 2;
+        has[i] = true;
+    }
+    Pass a1w, a0w; // with W: axis 1 writing W, axis 0 reading it
+    if (T) {
+        a1w = ax[1];
+        a1w.es_out = (long long)d[0] * rest;
+        a1w.gs_out = rest;
+        if ((rc = make_strided(plan, a0w, d[0], (int)rest, d[1], rest, (long long)d[0] * rest, ax[0].vidx, 0)))
+            return rc;
+        a0w.es_out = (long long)d[1] * rest;
+        a0w.gs_out = rest;
+        a0w.tag = 2;
+    }
+    Pass zf, zi;
+    const bool has_z = real || nl > 1;
+    if (real) {
+        if ((rc = make_real_z(plan, zf, P_R2C, lines)) || (rc = make_real_z(plan, zi, P_C2R, lines))) return rc;
+    } else if (has_z) {
+        if ((rc = make_contig(plan, zf, nl, lines, vz))) return rc;
+        zi = zf;
+        zi.sgn = -1;
+    }
+    zf.tag = zi.tag = 0;
+    zf.sgn = +1;
+    auto with = [](Pass q, int sgn, BufId src, BufId dst, long long off_in = 0, long long off_out = 0) {
+        q.sgn = sgn;
+        q.src = src;
+        q.dst = dst;
+        q.off_in = off_in;
+        q.off_out = off_out;
+        return q;
+    };
+    // forward: z, then the strided axes last to first; in -> out, then in place
+    auto& f = plan.fwd;
+    f.clear();
+    if (has_z) f.push_back(with(zf, +1, B_IN, B_OUT));
+    for (int i = r - 2; i >= (T ? 2 : 0); --i)
+        if (has[i]) f.push_back(with(ax[i], +1, f.empty() ? B_IN : B_OUT, B_OUT));
+    if (T) {
+        f.push_back(with(a1w, +1, f.empty() ? B_IN : B_OUT, B_WS));
+        f.push_back(with(a0w, +1, B_WS, B_OUT));
+    }
+    // inverse.  C2C: the first pass reads the input, the rest run in place on
+    // out.  R2C: the complex passes run in the workspace (after W, in its
+    // second spectrum), and the C2R reads it (or the input if it is alone).
+    auto& v = plan.inv;
+    v.clear();
+    const BufId work = real ? B_WS : B_OUT;
+    const long long woff = real && T ? (long long)spec_bytes : 0;
+    if (T) {
+        v.push_back(with(a1w, -1, B_IN, B_WS));
+        v.push_back(with(a0w, -1, B_WS, work, 0, woff));
+    }
+    for (int i = T ? 2 : 0; i <= r - 2; ++i)
+        if (has[i]) v.push_back(with(ax[i], -1, v.empty() ? B_IN : work, work, woff, woff));
+    if (real)
+        v.push_back(with(zi, -1, v.empty() ? B_IN : B_WS, B_OUT, v.empty() ? 0 : woff, 0));
+    else if (has_z)
+        v.push_back(with(zi, -1, v.empty() ? B_IN : B_OUT, B_OUT));
+    for (auto* list : {&plan.fwd, &plan.inv})
+        if (list->empty()) { // every extent 1: the identity
+            Pass c;
+            c.kind = P_COPY;
+            c.bytes = plan.esz;
+            c.src = B_IN;
+            c.dst = B_OUT;
+            list->push_back(c);
+        }
+    bool uses_ws = false;
+    for (auto* list : {&plan.fwd, &plan.inv})
+        for (const Pass& q : *list) uses_ws |= q.src == B_WS || q.dst == B_WS;
+    plan.ws_bytes = !uses_ws ? 0 : (real && T ? 2 * spec_bytes : spec_bytes);
+    plan.default_ws_bytes = plan.ws_bytes;
+    plan.poisson.clear();
+    plan.poisson_ws_bytes = 0;
     tile_passes(plan);
     return validate_extents(plan);
 }

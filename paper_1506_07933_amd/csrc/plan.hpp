@@ -92,6 +92,10 @@ public:
     // y with the unpack fused, z
     bool slab = false;
     int slab_p = 1;
+    // arrays of rank > 3 (Algorithm 2): the extents, first (slowest) to last;
+    // n0 n1 n2 then hold (product of the leading extents, second-to-last, last)
+    bool nd = false;
+    std::vector<int> dims;
     Pass sz, sy, sy_pack, spk, sx, sxi, supk, syi, syi_unpack, szi;
     std::map<int, void*> twiddles; // length -> device table
     void* ws = nullptr;
@@ -156,5 +160,6 @@ void rebuild_poisson(Plan& plan); // re-derive the Poisson pass list from fwd / 
 void apply_chunking(Plan& plan);  // interleave z/y (x^-1/z^-1) over plane chunks
 int build_pencil(Plan& plan, unsigned flags);
 int build_slab(Plan& plan, unsigned flags);
+int build_nd(Plan& plan, unsigned flags);
 
 } // namespace mifft

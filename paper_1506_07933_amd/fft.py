@@ -59,6 +59,15 @@ def plan_create_pencil(n0, n1, n2, p0, p1, kind=MIFFT_C2C, prec=MIFFT_FP32, flag
     return h.value
 
 
+def plan_create_nd(dims: Sequence[int], kind: int = MIFFT_C2C, prec: int = MIFFT_FP32,
+                   flags: int = MIFFT_HEURISTIC) -> int:
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int * len(dims))(*[int(d) for d in dims])
+    check(lib.mifft_plan_create_nd(ctypes.byref(h), len(dims), arr, kind, prec, flags),
+          "mifft_plan_create_nd")
+    return h.value
+
+
 def plan_create_slab(n0, n1, n2, p, kind=MIFFT_C2C, prec=MIFFT_FP32, flags=0) -> int:
     h = ctypes.c_void_p()
     check(lib.mifft_plan_create_slab(ctypes.byref(h), n0, n1, n2, p, kind, prec, flags),
@@ -136,25 +145,30 @@ def version() -> str:
 # ------------------------------------------------------------ tensor API
 
 class Plan:
-    """A planned 3-D transform of an (n0, n1, n2) grid on the current device.
+    """A planned transform of a C-order array on the current device: 3-D
+    (n0, n1, n2) grids, or any rank 1 .. 8 (axes transformed last to first,
+    Algorithm 2).
 
-    kind "c2c": forward / inverse map complex [n0][n1][n2] arrays.
-    kind "r2c": forward maps real [n0][n1][n2] to complex [n0][n1][n2//2+1],
-    inverse is the C2R map back; ``poisson`` solves lap(u) = f.
-    Neither direction is scaled.
+    kind "c2c": forward / inverse map complex arrays of `shape`.
+    kind "r2c": forward maps real `shape` to complex with the last extent
+    n // 2 + 1, inverse is the C2R map back; ``poisson`` (3-D only) solves
+    lap(u) = f.  Neither direction is scaled.
     """
 
     def __init__(self, shape: Sequence[int], kind: str = "c2c", prec: str = "fp32",
                  tune: bool = False):
         self.shape = tuple(int(s) for s in shape)
-        if len(self.shape) != 3:
-            raise ValueError("shape must have 3 extents")
+        if not 1 <= len(self.shape) <= 8:
+            raise ValueError("shape must have 1 .. 8 extents")
         self.kind, self.prec = kind, prec
-        self.handle = plan_create(*self.shape, _KIND[kind], _PREC[prec],
-                                  MIFFT_TUNE if tune else MIFFT_HEURISTIC)
+        flags = MIFFT_TUNE if tune else MIFFT_HEURISTIC
+        if len(self.shape) == 3:
+            self.handle = plan_create(*self.shape, _KIND[kind], _PREC[prec], flags)
+        else:
+            self.handle = plan_create_nd(self.shape, _KIND[kind], _PREC[prec], flags)
         self.cdtype, self.rdtype = _CDTYPE[prec], _RDTYPE[prec]
-        n0, n1, n2 = self.shape
-        self.spec_shape = (n0, n1, n2 // 2 + 1) if kind == "r2c" else self.shape
+        last = self.shape[-1]
+        self.spec_shape = self.shape[:-1] + (last // 2 + 1,) if kind == "r2c" else self.shape
 
     @property
     def workspace_bytes(self) -> int:
@@ -358,7 +372,7 @@ class SlabPlan:
 
 
 __all__ = ["Plan", "PencilPlan", "SlabPlan", "MifftError", "plan_create", "plan_create_pencil",
-           "plan_create_slab", "execute_forward", "execute_inverse", "execute_forward_ws",
+           "plan_create_slab", "plan_create_nd", "execute_forward", "execute_inverse", "execute_forward_ws",
            "execute_inverse_ws", "execute_pencil_stages", "execute_slab_stages", "poisson_solve",
            "workspace_bytes", "poisson_ws_bytes", "plan_destroy", "plan_describe",
            "profile_begin", "profile_end", "version"]

@@ -29,7 +29,7 @@ def test_header_declares_the_boundary():
     for must in ("mifft_plan_create", "mifft_execute_forward", "mifft_execute_inverse",
                  "mifft_plan_destroy", "mifft_last_error", "mifft_plan_create_pencil",
                  "mifft_execute_pencil_stages", "mifft_plan_create_slab",
-                 "mifft_execute_slab_stages", "mifft_batch_create",
+                 "mifft_execute_slab_stages", "mifft_plan_create_nd", "mifft_batch_create",
                  "mifft_batch_execute_forward", "mifft_poisson_solve"):
         assert must in names
 
@@ -102,6 +102,31 @@ def test_slab_validation(L):
     assert b"slab" in L.mifft_last_error()
     assert L.mifft_execute_pencil_stages(h, 1, buf, buf, buf, buf, None) == 5
     assert L.mifft_workspace_bytes(h) == 0
+    assert L.mifft_plan_destroy(h) == 0
+
+
+def test_nd_validation(L):
+    h = ctypes.c_void_p()
+    f = L.mifft_plan_create_nd
+
+    def dims(*d):
+        return (ctypes.c_int * len(d))(*d)
+    assert f(ctypes.byref(h), 0, dims(4), 0, 0, 0) == 1               # rank 0
+    assert f(ctypes.byref(h), 9, dims(*([2] * 9)), 0, 0, 0) == 1       # rank above MIFFT_MAX_RANK
+    assert f(ctypes.byref(h), 4, None, 0, 0, 0) == 1
+    assert f(None, 4, dims(2, 2, 2, 2), 0, 0, 0) == 1
+    assert f(ctypes.byref(h), 4, dims(2, 0, 2, 2), 0, 0, 0) == 1
+    assert f(ctypes.byref(h), 4, dims(2, 7, 2, 2), 0, 0, 0) == 2       # prime factor 7
+    assert f(ctypes.byref(h), 4, dims(2, 2, 2, 9), 1, 0, 0) == 2       # R2C, odd last extent
+    assert f(ctypes.byref(h), 4, dims(1024, 1024, 1024, 2), 0, 0, 2) == 2  # 2^31 elements
+    assert f(ctypes.byref(h), 4, dims(2, 2, 2, 2), 0, 0, 1) == 2       # MIFFT_TUNE: rank <= 3 only
+    assert f(ctypes.byref(h), 4, dims(2, 2, 2, 2), 2, 0, 0) == 1       # bad kind
+    assert f(ctypes.byref(h), 2, dims(4, 7), 0, 0, 2) == 2             # rank <= 3 checks as 3-D
+    # plan-only N-D plans describe but never execute or solve Poisson
+    assert f(ctypes.byref(h), 5, dims(4, 3, 2, 5, 6), 1, 1, 2) == 0
+    buf = ctypes.c_void_p(0x10000)
+    assert L.mifft_execute_forward(h, buf, buf, None) == 5
+    assert L.mifft_poisson_solve(h, buf, buf, None, None) == 5
     assert L.mifft_plan_destroy(h) == 0
 
 

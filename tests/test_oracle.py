@@ -390,6 +390,25 @@ def test_fftnd_direct_sum(shape, sign):
     assert rel_l2(oracle.fftnd_c2c(x, sign), _direct_dft_nd(x, sign)) < 1e-13
 
 
+def test_dftnd_at_sampled_definition():
+    """The sampled N-D definition (used where the full oracle is too large)
+    against the dense direct sum on tiny arrays, and against the FFT oracle
+    at random outputs of a 4-D array."""
+    from oracle.brute import dftnd_at
+    for shape in [(2, 3, 4, 5), (3, 1, 2, 2, 4), (7,)]:
+        x = _rand_c(shape, 31)
+        allk = np.stack(np.unravel_index(np.arange(x.size), shape), axis=1)
+        for sign in (-1, 1):
+            got = dftnd_at(x, allk, sign, chunk_rows=3).reshape(shape)
+            assert rel_l2(got, _direct_dft_nd(x, sign)) < 1e-13
+    x = _rand_c((8, 6, 10, 12), 32)
+    rng = np.random.default_rng(33)
+    ks = np.stack([rng.integers(0, n, 20) for n in x.shape], axis=1)
+    ref = oracle.fftnd_c2c(x, -1)[tuple(ks.T)]
+    assert rel_l2(dftnd_at(x.astype(np.complex64), ks, -1), oracle.fftnd_c2c(x.astype(np.complex64), -1)[tuple(ks.T)]) < 1e-13
+    assert rel_l2(dftnd_at(x, ks, -1, chunk_rows=7), ref) < 1e-13
+
+
 def test_fftnd_matches_numpy_and_3d():
     x = _rand_c((4, 6, 10, 8), 27)
     assert rel_l2(oracle.fftnd_c2c(x, -1), np.fft.fftn(x)) < 1e-13

@@ -287,3 +287,88 @@ def test_slab_passes_stay_inside_the_share(shape, p):
             rc = lib.mifft_plan_create_slab(ctypes.byref(h), *shape, p, kind, prec, MIFFT_PLAN_ONLY)
             assert rc == 0, (shape, p, kind, prec, lib.mifft_last_error())
             plan_destroy(h.value)
+
+
+def nd_only(dims, kind=0, prec=0):
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int * len(dims))(*dims)
+    rc = lib.mifft_plan_create_nd(ctypes.byref(h), len(dims), arr, kind, prec, MIFFT_PLAN_ONLY)
+    assert rc == 0, lib.mifft_last_error()
+    text = plan_describe(h.value)
+    ws = lib.mifft_workspace_bytes(h.value)
+    plan_destroy(h.value)
+    passes = []
+    for line in text.splitlines():
+        d = dict(kv.split("=") for kv in line.split()[1:])
+        d["dir"] = line.split()[0]
+        passes.append(d)
+    return passes, ws, text
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_nd_4d_pass_list(kind):
+    """512 x 256 x 128 x 64 (the paper's 4-D case): the last axis as
+    contiguous lines, then one strided pass per earlier axis, last to first,
+    each with the elements after the axis as its columns and the index range
+    before it as its groups.  Axis 0's stride (256 x 128 x N2c elements) is
+    large, so axis 1 writes the transposed intermediate W[k1][x0][rest] and
+    axis 0 reads it with stride `rest`; the inverse runs axis 1 (into W),
+    axis 0 (back to the standard layout), axis 2, then the last axis.  R2C
+    halves the last axis; its inverse keeps the input (two spectra of
+    workspace)."""
+    d = (512, 256, 128, 64)
+    nc = 33 if kind else 64
+    rest = 128 * nc
+    passes, ws, _ = nd_only(d, kind)
+    fwd = [p for p in passes if p["dir"] == "forward"]
+    inv = [p for p in passes if p["dir"] == "inverse"]
+    assert fwd[0]["kind"] == ("r2c_z" if kind else "contig")
+    assert int(fwd[0]["lines"]) == 512 * 256 * 128
+    a2, a1, a0 = fwd[1:]
+    assert ints(a2, "L", "cols", "groups") == [128, nc, 512 * 256]
+    assert a2["es"] == "%d/%d" % (nc, nc) and a2["gs"] == "%d/%d" % (128 * nc, 128 * nc)
+    assert int(a2["B"]) == 64      # 131072 groups of 33 / 64 columns: one tile per group
+    assert ints(a1, "L", "cols", "groups") == [256, rest, 512]
+    assert a1["es"] == "%d/%d" % (rest, 512 * rest) and a1["gs"] == "%d/%d" % (256 * rest, rest)
+    assert ints(a0, "L", "cols", "groups") == [512, rest, 256]
+    assert a0["es"] == "%d/%d" % (rest, 256 * rest) and a0["gs"] == "%d/%d" % (512 * rest, rest)
+    assert all(q["sgn"] == "1" for q in fwd[1:])
+    assert [int(q["L"]) for q in inv] == [256, 512, 128, 32 if kind else 64]
+    assert all(q["sgn"] == "-1" for q in inv[:3])
+    assert inv[-1]["kind"] == ("c2r_z" if kind else "contig")
+    spec = 512 * 256 * 128 * nc * 8
+    assert ws == (2 * spec if kind else spec)
+
+
+def test_nd_small_axis0_stride_keeps_the_standard_layout():
+    passes, ws, _ = nd_only((8, 4, 6, 10))
+    fwd = [p for p in passes if p["dir"] == "forward"]
+    assert [int(q["L"]) for q in fwd] == [10, 6, 4, 8]
+    assert fwd[-1]["es"] == "240/240" and ws == 0
+
+
+def test_nd_rank3_is_the_3d_plan():
+    h = ctypes.c_void_p()
+    assert lib.mifft_plan_create_nd(ctypes.byref(h), 3, (ctypes.c_int * 3)(64, 48, 40), 0, 0,
+                                    MIFFT_PLAN_ONLY) == 0
+    a = plan_describe(h.value)
+    plan_destroy(h.value)
+    assert lib.mifft_plan_create(ctypes.byref(h), 64, 48, 40, 0, 0, MIFFT_PLAN_ONLY) == 0
+    b = plan_describe(h.value)
+    plan_destroy(h.value)
+    assert a == b
+    assert lib.mifft_plan_create_nd(ctypes.byref(h), 1, (ctypes.c_int * 1)(96), 1, 1,
+                                    MIFFT_PLAN_ONLY) == 0
+    c = plan_describe(h.value)
+    plan_destroy(h.value)
+    assert "r2c_z" in c and "strided" not in c
+
+
+@pytest.mark.parametrize("dims", [(512, 256, 128, 64), (2, 3, 4, 5, 6), (1, 1, 1, 1), (8, 1, 1, 6),
+                                  (3, 1, 5, 1, 2, 1, 4, 2), (1024, 1024, 2, 1), (16, 16, 16, 1024)])
+def test_nd_passes_stay_inside_the_buffers(dims):
+    for kind in (0, 1):
+        if kind and dims[-1] % 2:
+            continue
+        for prec in (0, 1):
+            nd_only(dims, kind, prec)
