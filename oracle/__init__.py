@@ -19,6 +19,10 @@ Contents
     ``c2r_z`` is the z-only C2R its inverse ends with.
   * ``fftnd_c2c / fftnd_r2c / fftnd_c2r`` -- transforms of any rank in the
     axis order of Algorithm 2 (last axis first; the inverse first axis first).
+  * ``spectral_multiplier / spectral_apply / gradient / divergence`` -- more
+    of the "fast spectral operators" of Sec. 1 on the periodic box: Laplacian,
+    Helmholtz solve, partial derivatives (the even-length Nyquist mode of a
+    derivative set to zero), gradient and divergence.
   * ``brute`` submodule -- the direct O(N^2) DFT used to pin the FFT.
 
 Conventions (readings of the paper, listed in the design notes): forward uses
@@ -309,3 +313,67 @@ def fftnd_c2r(y, n_last: int) -> np.ndarray:
     for ax in range(a.ndim - 1):
         a = fft_axis(a, ax, +1)
     return c2r_z(a, n_last)
+
+
+# ---- spectral operators on [0, 2 pi)^3 (Sec. 1, "fast spectral operators") ----
+
+OP_POISSON, OP_LAPLACIAN, OP_HELMHOLTZ, OP_DX, OP_DY, OP_DZ = 0, 1, 2, 3, 4, 5
+
+
+def spectral_multiplier(shape, op: int, alpha: float = 0.0) -> np.ndarray:
+    """The multiplier m(k) on the half spectrum [n0][n1][n2//2+1] of a real
+    [n0][n1][n2] grid.  Integer wavenumbers: k0 = i0 for i0 < n0/2, else
+    i0 - n0 (likewise k1); k2 = i2 >= 0.
+      OP_POISSON    -1/|k|^2 (0 at k = 0): u solves lap(u) = f
+      OP_LAPLACIAN  -|k|^2: u = lap(f)
+      OP_HELMHOLTZ  1/(alpha + |k|^2) (0 where that vanishes): u solves
+                    alpha u - lap(u) = f
+      OP_DX/DY/DZ   i k_j: u = d f / d x_j; for an even n_j the mode
+                    i_j = n_j/2 is set to 0 (its sign is ambiguous and the
+                    derivative of a real field must stay real)."""
+    n0, n1, n2 = shape
+    i0 = np.arange(n0)[:, None, None]
+    i1 = np.arange(n1)[None, :, None]
+    i2 = np.arange(n2 // 2 + 1)[None, None, :]
+    k0 = np.where(2 * i0 < n0, i0, i0 - n0).astype(np.float64)
+    k1 = np.where(2 * i1 < n1, i1, i1 - n1).astype(np.float64)
+    k2 = i2.astype(np.float64)
+    kk = k0 ** 2 + k1 ** 2 + k2 ** 2
+    full = (n0, n1, n2 // 2 + 1)
+    if op == OP_POISSON:
+        with np.errstate(divide="ignore"):
+            m = np.where(kk == 0, 0.0, -1.0 / np.where(kk == 0, 1.0, kk))
+    elif op == OP_LAPLACIAN:
+        m = -kk
+    elif op == OP_HELMHOLTZ:
+        den = alpha + kk
+        m = np.where(den == 0, 0.0, 1.0 / np.where(den == 0, 1.0, den))
+    elif op in (OP_DX, OP_DY, OP_DZ):
+        j = op - OP_DX
+        k, i, n = ((k0, i0, n0), (k1, i1, n1), (k2, i2, n2))[j]
+        m = np.where(2 * i == n, 0.0, 1j * k)
+    else:
+        raise ValueError("unknown operator %d" % op)
+    return np.broadcast_to(m, full).astype(np.complex128)
+
+
+def spectral_apply(f, op: int, alpha: float = 0.0) -> np.ndarray:
+    """u = C2R(m * R2C(f)) / N: the operator applied to a real periodic field."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.size
+    return fft3d_c2r(fft3d_r2c(f) * spectral_multiplier(f.shape, op, alpha), f.shape[2]) / n
+
+
+def gradient(f) -> list:
+    """(df/dx0, df/dx1, df/dx2) of a real periodic field."""
+    return [spectral_apply(f, op) for op in (OP_DX, OP_DY, OP_DZ)]
+
+
+def divergence(v0, v1, v2) -> np.ndarray:
+    """d v0/dx0 + d v1/dx1 + d v2/dx2, summed in the spectrum and brought back
+    with one C2R."""
+    v = [np.asarray(a, dtype=np.float64) for a in (v0, v1, v2)]
+    shape = v[0].shape
+    acc = sum(fft3d_r2c(a) * spectral_multiplier(shape, op)
+              for a, op in zip(v, (OP_DX, OP_DY, OP_DZ)))
+    return fft3d_c2r(acc, shape[2]) / v[0].size

@@ -17,6 +17,9 @@ Each pin is chosen so a plausible mistake fails at least one test:
   * transforms of any rank against a direct N-D DFT sum over all index
     pairs, numpy.fft.fftn / rfftn / irfftn, and the 3-D oracle for a
     leading extent of 1
+  * the spectral operators (Laplacian, Helmholtz, derivatives, gradient,
+    divergence) against closed forms for sums of Fourier modes, the
+    Nyquist-mode convention, and numpy's frequency grids
 """
 import os
 
@@ -291,6 +294,81 @@ def test_pencil_row_group_emulation():
         b = oracle.pencil_unpack(recv, n1l)
         got = oracle.fft_axis(b, 1, -1)
         assert rel_l2(got, ref[:, :, j * m:(j + 1) * m]) < 1e-13
+
+
+# ------------------------------------------------- other spectral operators
+
+def _modes(n, seed):
+    ks, amp, phase, _ = synth.poisson_modes(n, seed=seed)
+    return ks, amp, phase
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_laplacian_and_helmholtz_closed_form(n):
+    """lap cos(k.x + p) = -|k|^2 cos(k.x + p); (alpha - lap) u = f for
+    u = cos(k.x + p) / (alpha + |k|^2)."""
+    ks, amp, phase = _modes(n, 40 + n)
+    f = synth.mode_sum(n, ks, amp, phase)
+    kk = np.sum(ks * ks, axis=1).astype(np.float64)
+    lap = oracle.spectral_apply(f, oracle.OP_LAPLACIAN)
+    assert rel_l2(lap, synth.mode_sum(n, ks, -amp * kk, phase)) < 1e-12
+    for alpha in (0.5, 3.0):
+        u = oracle.spectral_apply(f, oracle.OP_HELMHOLTZ, alpha)
+        assert rel_l2(u, synth.mode_sum(n, ks, amp / (alpha + kk), phase)) < 1e-12
+    # alpha = 0 is the Poisson solve with the opposite sign
+    assert rel_l2(oracle.spectral_apply(f, oracle.OP_HELMHOLTZ, 0.0), -oracle.poisson_solve(f)) < 1e-13
+
+
+@pytest.mark.parametrize("n", [16, 18])
+def test_gradient_and_divergence_closed_form(n):
+    """d/dx_j cos(k.x + p) = k_j cos(k.x + p + pi/2), for modes below the
+    Nyquist index; the divergence of three mode sums is the sum of those."""
+    ks, amp, phase = _modes(n, 50 + n)
+    f = synth.mode_sum(n, ks, amp, phase)
+    g = oracle.gradient(f)
+    for j in range(3):
+        ref = synth.mode_sum(n, ks, amp * ks[:, j], phase + np.pi / 2)
+        assert rel_l2(g[j], ref) < 1e-12
+    rng = np.random.default_rng(n)
+    amps = [rng.standard_normal(len(ks)) for _ in range(3)]
+    v = [synth.mode_sum(n, ks, a, phase) for a in amps]
+    d = oracle.divergence(*v)
+    ref = sum(synth.mode_sum(n, ks, a * ks[:, j], phase + np.pi / 2) for j, a in enumerate(amps))
+    assert rel_l2(d, ref) < 1e-12
+    # the divergence of a gradient is the Laplacian (no Nyquist content here)
+    assert rel_l2(oracle.divergence(*g), oracle.spectral_apply(f, oracle.OP_LAPLACIAN)) < 1e-12
+
+
+def test_derivative_nyquist_mode_is_zero():
+    """On an even grid the highest mode cos(n x / 2) = (-1)^i has no
+    well-defined derivative sign; the convention sets it to zero.  Odd grids
+    have no such mode and differentiate every mode."""
+    n = 8
+    i = np.arange(n)
+    f = np.broadcast_to(((-1.0) ** i)[:, None, None], (n, n, n)).copy()
+    for op in (oracle.OP_DX, oracle.OP_DY, oracle.OP_DZ):
+        assert np.max(np.abs(oracle.spectral_apply(np.moveaxis(f, 0, op - oracle.OP_DX), op))) < 1e-13
+    m = oracle.spectral_multiplier((6, 5, 8), oracle.OP_DX)
+    assert np.all(m[3] == 0) and np.all(m[2] == 2j) and np.all(m[4] == -2j)
+    m = oracle.spectral_multiplier((6, 5, 8), oracle.OP_DY)
+    assert np.all(m[:, 2] == 2j) and np.all(m[:, 3] == -2j)      # n1 = 5: no Nyquist index
+    m = oracle.spectral_multiplier((6, 5, 8), oracle.OP_DZ)
+    assert np.all(m[..., 4] == 0) and np.all(m[..., 3] == 3j)
+
+
+def test_spectral_multipliers_match_numpy_frequencies():
+    shape = (6, 10, 12)
+    k0 = np.fft.fftfreq(6, 1 / 6)[:, None, None]
+    k1 = np.fft.fftfreq(10, 1 / 10)[None, :, None]
+    k2 = np.fft.rfftfreq(12, 1 / 12)[None, None, :]
+    kk = k0 ** 2 + k1 ** 2 + k2 ** 2
+    np.testing.assert_allclose(oracle.spectral_multiplier(shape, oracle.OP_LAPLACIAN), np.broadcast_to(-kk, (6, 10, 7)))
+    p = oracle.spectral_multiplier(shape, oracle.OP_POISSON)
+    assert p[0, 0, 0] == 0
+    np.testing.assert_allclose(p.ravel()[1:], -1 / kk.ravel()[1:])
+    # the Poisson multiplier agrees with the C oracle's multiply
+    y = _rand_c((6, 10, 7), 60)
+    np.testing.assert_allclose(y * p, oracle.poisson_half(y, 12), rtol=1e-14, atol=1e-15)
 
 
 # -------------------------------------------------------------- slab maps
