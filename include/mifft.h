@@ -257,6 +257,43 @@ size_t mifft_poisson_ws_bytes(mifft_plan plan);
 int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void* stream);
 
 /*
+ * Spectral operators on the periodic box [0, 2 pi)^3 with a 3-D R2C plan
+ * (more of the "fast spectral operators" listed in Sec. 1): u = C2R(m(k) *
+ * R2C(f)) / (n0 n1 n2), with integer wavenumbers k0 = i0 below n0/2, else
+ * i0 - n0 (likewise k1), k2 = i2:
+ *   MIFFT_OP_POISSON    -1/|k|^2, 0 at k = 0 (u solves lap(u) = f; as
+ *                       mifft_poisson_solve)
+ *   MIFFT_OP_LAPLACIAN  -|k|^2 (u = lap(f))
+ *   MIFFT_OP_HELMHOLTZ  1/(alpha + |k|^2), 0 where that vanishes (u solves
+ *                       alpha u - lap(u) = f)
+ *   MIFFT_OP_DX/DY/DZ   i k_j (u = df/dx_j); on an even axis the Nyquist
+ *                       mode i_j = n_j/2 is set to 0
+ * The x-forward, the multiply and the x-inverse run as one kernel (for
+ * n0 > 1).  f, u and the outputs below are real [n0][n1][n2] device arrays;
+ * f is preserved; outputs must not overlap inputs.  ws: NULL (the plan's
+ * own workspace; calls on one plan must then not overlap) or a caller buffer
+ * of mifft_poisson_ws_bytes (apply) or mifft_spectral_ws_bytes (gradient,
+ * divergence) bytes.  Errors: BADPLAN for a plan that is not a 3-D R2C
+ * plan, INVALID for NULL / unaligned / aliased fields or an unknown op.
+ */
+#define MIFFT_OP_POISSON 0
+#define MIFFT_OP_LAPLACIAN 1
+#define MIFFT_OP_HELMHOLTZ 2
+#define MIFFT_OP_DX 3
+#define MIFFT_OP_DY 4
+#define MIFFT_OP_DZ 5
+int mifft_spectral_apply(mifft_plan plan, int op, double alpha, const void* f, void* u, void* ws, void* stream);
+size_t mifft_spectral_ws_bytes(mifft_plan plan);
+/* (df/dx, df/dy, df/dz): one forward transform, then per component the
+ * fused multiply and the inverse. */
+int mifft_spectral_gradient(mifft_plan plan, const void* f, void* gx, void* gy, void* gz, void* ws,
+                            void* stream);
+/* dvx/dx + dvy/dy + dvz/dz: per component the forward transform and the fused
+ * multiply, summed in the spectrum; then one inverse. */
+int mifft_spectral_divergence(mifft_plan plan, const void* vx, const void* vy, const void* vz, void* d,
+                              void* ws, void* stream);
+
+/*
  * mifft_batch_create -- plan `count` (1 .. 128) independent 3-D C2C transforms
  * of uneven sizes (dims holds n0, n1, n2 per transform) that run as ONE
  * launch of a persistent kernel: workgroups pull (transform, pass, tile)

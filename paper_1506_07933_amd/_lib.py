@@ -18,6 +18,7 @@ MIFFT_HEURISTIC, MIFFT_TUNE, MIFFT_PLAN_ONLY, MIFFT_BATCH_KERNELS = 0, 1, 2, 4
 MIFFT_STAGE_Z, MIFFT_STAGE_PACK, MIFFT_STAGE_UNPACK, MIFFT_STAGE_Y = 1, 2, 4, 8
 MIFFT_SLAB_Z, MIFFT_SLAB_Y, MIFFT_SLAB_X, MIFFT_SLAB_PACK, MIFFT_SLAB_UNPACK = 1, 2, 4, 8, 16
 MIFFT_SLAB_INVERSE = 256
+MIFFT_OP_POISSON, MIFFT_OP_LAPLACIAN, MIFFT_OP_HELMHOLTZ, MIFFT_OP_DX, MIFFT_OP_DY, MIFFT_OP_DZ = range(6)
 STATUS = {0: "MIFFT_OK", 1: "MIFFT_ERR_INVALID", 2: "MIFFT_ERR_UNSUPPORTED",
           3: "MIFFT_ERR_NOMEM", 4: "MIFFT_ERR_DEVICE", 5: "MIFFT_ERR_BADPLAN"}
 
@@ -40,6 +41,10 @@ SIGNATURES = {
     "mifft_execute_slab_stages": (_i, [_vp, _u, _cvp, _vp, _vp, _vp, _vp]),
     "mifft_poisson_ws_bytes": (_sz, [_vp]),
     "mifft_poisson_solve": (_i, [_vp, _cvp, _vp, _vp, _vp]),
+    "mifft_spectral_apply": (_i, [_vp, _i, ctypes.c_double, _cvp, _vp, _vp, _vp]),
+    "mifft_spectral_ws_bytes": (_sz, [_vp]),
+    "mifft_spectral_gradient": (_i, [_vp, _cvp, _vp, _vp, _vp, _vp, _vp]),
+    "mifft_spectral_divergence": (_i, [_vp, _cvp, _cvp, _cvp, _vp, _vp, _vp]),
     "mifft_batch_create": (_i, [_vpp, _i, ctypes.POINTER(ctypes.c_int), _i, _i, _u]),
     "mifft_batch_execute_forward": (_i, [_vp, _vpp, _vpp, _vp]),
     "mifft_batch_graph_launch": (_i, [_vp, _vpp, _vpp, _vp]),

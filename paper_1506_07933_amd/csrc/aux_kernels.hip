@@ -1,6 +1,7 @@
 // aux_kernels.hip -- twiddle generation, spectral Poisson multiply, standalone
 // pack / unpack of the row all-to-all, and a plain copy.
 #include "aux_kernels.hpp"
+#include "spectral.hpp"
 
 namespace mifft {
 
@@ -42,37 +43,36 @@ hipError_t launch_twiddles(cx<T>* w, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-// U[i0][i1][k2] *= -scale / |k|^2 on the half spectrum, U[0][0][0] = 0.
+// Standalone spectral multiply on the half spectrum [n0][n1][n2c] of an
+// n0 x n1 x n2 real grid: dst = m(k) src (dst += m(k) src with acc), m from
+// spectral_mul; src may equal dst.
 template <typename T>
-__global__ void k_poisson(cx<T>* u, int n0, int n1, int n2c, T scale, long long total)
+__global__ void k_spectral(const cx<T>* src, cx<T>* dst, int n0, int n1, int n2c, int n2, int op, T scale,
+                           T alpha, int acc, long long total)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    const int k2 = (int)(i % n2c);
+    const int i2 = (int)(i % n2c);
     const long long r = i / n2c;
     const int i1 = (int)(r % n1);
     const int i0 = (int)(r / n1);
-    const long long k0 = (2 * i0 < n0) ? i0 : i0 - n0;
-    const long long k1 = (2 * i1 < n1) ? i1 : i1 - n1;
-    const long long kk = k0 * k0 + k1 * k1 + (long long)k2 * k2;
-    cx<T> v = u[i];
-    if (kk == 0) {
-        v = cx<T>{T(0), T(0)};
-    } else {
-        const T f = -scale / (T)kk;
-        v.x *= f;
-        v.y *= f;
+    cx<T> v = spectral_mul<T>(op, i0, i1, i2, n0, n1, n2, scale, alpha, src[i]);
+    if (acc) {
+        const cx<T> o = dst[i];
+        v.x += o.x;
+        v.y += o.y;
     }
-    u[i] = v;
+    dst[i] = v;
 }
 
 template <typename T>
-hipError_t launch_poisson(cx<T>* u, int n0, int n1, int n2c, T scale, hipStream_t s)
+hipError_t launch_spectral(const cx<T>* src, cx<T>* dst, int n0, int n1, int n2c, int n2, int op, T scale,
+                           T alpha, int acc, hipStream_t s)
 {
     const long long total = (long long)n0 * n1 * n2c;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_poisson<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, u, n0,
-                       n1, n2c, scale, total);
+    hipLaunchKernelGGL(k_spectral<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, n0,
+                       n1, n2c, n2, op, scale, alpha, acc, total);
     return hipGetLastError();
 }
 
@@ -160,8 +160,10 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
 
 template hipError_t launch_twiddles<float>(cx<float>*, int, hipStream_t);
 template hipError_t launch_twiddles<double>(cx<double>*, int, hipStream_t);
-template hipError_t launch_poisson<float>(cx<float>*, int, int, int, float, hipStream_t);
-template hipError_t launch_poisson<double>(cx<double>*, int, int, int, double, hipStream_t);
+template hipError_t launch_spectral<float>(const cx<float>*, cx<float>*, int, int, int, int, int, float, float,
+                                           int, hipStream_t);
+template hipError_t launch_spectral<double>(const cx<double>*, cx<double>*, int, int, int, int, int, double,
+                                            double, int, hipStream_t);
 template hipError_t launch_pack<float>(const cx<float>*, cx<float>*, int, int, int, int, hipStream_t);
 template hipError_t launch_pack<double>(const cx<double>*, cx<double>*, int, int, int, int, hipStream_t);
 template hipError_t launch_unpack<float>(const cx<float>*, cx<float>*, int, int, int, int, hipStream_t);

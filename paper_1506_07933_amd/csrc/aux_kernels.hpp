@@ -7,7 +7,8 @@ namespace mifft {
 
 template <typename T> hipError_t launch_twiddles(cx<T>* w, int n, hipStream_t s);
 template <typename T>
-hipError_t launch_poisson(cx<T>* u, int n0, int n1, int n2c, T scale, hipStream_t s);
+hipError_t launch_spectral(const cx<T>* src, cx<T>* dst, int n0, int n1, int n2c, int n2, int op, T scale,
+                           T alpha, int acc, hipStream_t s);
 template <typename T>
 hipError_t launch_pack(const cx<T>* a, cx<T>* s, int n0l, int n1l, int p1, int M, hipStream_t st);
 template <typename T>

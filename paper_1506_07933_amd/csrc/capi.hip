@@ -13,6 +13,7 @@
 
 #include "aux_kernels.hpp"
 #include "plan.hpp"
+#include "spectral.hpp"
 
 namespace mifft {
 const char* last_error_cstr();
@@ -27,6 +28,11 @@ int tune_plan(Plan& plan);
 using namespace mifft;
 
 struct mifft_plan_s : public Plan {};
+
+static_assert(MIFFT_OP_POISSON == OP_POISSON && MIFFT_OP_LAPLACIAN == OP_LAPLACIAN &&
+                  MIFFT_OP_HELMHOLTZ == OP_HELMHOLTZ && MIFFT_OP_DX == OP_DX && MIFFT_OP_DY == OP_DY &&
+                  MIFFT_OP_DZ == OP_DZ,
+              "operator codes of the C ABI and the kernels differ");
 
 static std::mutex g_live_mu;
 static std::set<const void*> g_live;
@@ -433,21 +439,133 @@ int mifft_execute_inverse(mifft_plan plan, const void* in, void* out, void* stre
     return run_passes(*plan, plan->inv, in, out, plan->ws, nullptr, nullptr, (hipStream_t)stream);
 }
 
-int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void* stream)
+static int check_spectral(mifft_plan plan, const void* ws)
 {
-    clear_error();
     if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
-    if (plan->pencil || plan->slab || plan->nd || plan->kind != MIFFT_R2C)
-        return set_error(MIFFT_ERR_BADPLAN, "the Poisson solve needs a 3-D R2C plan");
+    if (plan->pencil || plan->slab || plan->nd || plan->kind != MIFFT_R2C || plan->poisson_mul < 0)
+        return set_error(MIFFT_ERR_BADPLAN, "spectral operators need a 3-D R2C plan");
     if (plan->plan_only) return set_error(MIFFT_ERR_BADPLAN, "plan was built with MIFFT_PLAN_ONLY");
-    if (!f || !u) return set_error(MIFFT_ERR_INVALID, "f / u must not be NULL");
-    if (!aligned16(f) || !aligned16(u) || (ws && !aligned16(ws)))
-        return set_error(MIFFT_ERR_INVALID, "pointers must be 16-byte aligned");
+    if (ws && !aligned16(ws)) return set_error(MIFFT_ERR_INVALID, "ws must be 16-byte aligned");
+    return MIFFT_OK;
+}
+
+static int check_field(const void* p, const char* name)
+{
+    if (!p) return set_error(MIFFT_ERR_INVALID, "%s must not be NULL", name);
+    if (!aligned16(p)) return set_error(MIFFT_ERR_INVALID, "%s must be 16-byte aligned", name);
+    return MIFFT_OK;
+}
+
+static Pass renamed(Pass q, BufId from, BufId to)
+{
+    if (q.src == from) q.src = to;
+    if (q.dst == from) q.dst = to;
+    return q;
+}
+
+int mifft_spectral_apply(mifft_plan plan, int op, double alpha, const void* f, void* u, void* ws, void* stream)
+{
+    clear_error();
+    int rc = check_spectral(plan, ws);
+    if (rc) return rc;
+    if (op < MIFFT_OP_POISSON || op > MIFFT_OP_DZ) return set_error(MIFFT_ERR_INVALID, "unknown operator %d", op);
+    if ((rc = check_field(f, "f")) || (rc = check_field(u, "u"))) return rc;
     if (f == u) return set_error(MIFFT_ERR_INVALID, "f and u must not overlap");
+    std::vector<Pass> list = plan->poisson;
+    list[plan->poisson_mul].op = op;
+    list[plan->poisson_mul].alpha = alpha;
     char* w = (char*)(ws ? ws : plan->ws);
     const size_t half = plan->poisson_ws_bytes / 2;
-    return run_passes(*plan, plan->poisson, f, u, nullptr, w, w + half, (hipStream_t)stream);
+    return run_passes(*plan, list, f, u, nullptr, w, w + half, (hipStream_t)stream);
+}
+
+int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void* stream)
+{
+    return mifft_spectral_apply(plan, MIFFT_OP_POISSON, 0.0, f, u, ws, stream);
+}
+
+size_t mifft_spectral_ws_bytes(mifft_plan plan)
+{
+    if (!plan || !is_live(plan)) return 0;
+    return plan->spectral_ws_bytes;
+}
+
+// The Poisson pass list is forward part F, multiply M, inverse part I; M
+// reads and writes the buffer D that F leaves the spectrum in.  Gradient: F
+// once, then per component M (D -> E, the derivative) and I (on E): E is the
+// other half of the Poisson workspace where F's spectrum stays untouched by
+// I, else the third buffer.  Divergence: per component F and M (D -> C, the
+// third buffer, adding from the second component on), then I on C once.
+int mifft_spectral_gradient(mifft_plan plan, const void* f, void* gx, void* gy, void* gz, void* ws, void* stream)
+{
+    clear_error();
+    int rc = check_spectral(plan, ws);
+    if (rc) return rc;
+    if ((rc = check_field(f, "f")) || (rc = check_field(gx, "gx")) || (rc = check_field(gy, "gy")) ||
+        (rc = check_field(gz, "gz")))
+        return rc;
+    void* g[3] = {gx, gy, gz};
+    for (int j = 0; j < 3; ++j) {
+        if (g[j] == f) return set_error(MIFFT_ERR_INVALID, "the outputs must not overlap f");
+        for (int k = 0; k < j; ++k)
+            if (g[j] == g[k]) return set_error(MIFFT_ERR_INVALID, "the outputs must be distinct");
+    }
+    const std::vector<Pass>& P = plan->poisson;
+    const int mi = plan->poisson_mul;
+    const Pass& M = P[mi];
+    const BufId D = M.src;
+    const BufId E = M.kind == P_POISSON_X ? (D == B_SEND ? B_RECV : B_SEND) : B_WS;
+    char* w = (char*)(ws ? ws : plan->ws);
+    const size_t half = plan->poisson_ws_bytes / 2;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<Pass> fwd(P.begin(), P.begin() + mi);
+    if ((rc = run_passes(*plan, fwd, f, nullptr, w + 2 * half, w, w + half, s))) return rc;
+    for (int j = 0; j < 3; ++j) {
+        std::vector<Pass> list;
+        Pass m = M;
+        m.src = D;
+        m.dst = E;
+        m.op = MIFFT_OP_DX + j;
+        m.acc = 0;
+        list.push_back(m);
+        for (size_t k = mi + 1; k < P.size(); ++k) list.push_back(renamed(P[k], D, E));
+        if ((rc = run_passes(*plan, list, nullptr, g[j], w + 2 * half, w, w + half, s))) return rc;
+    }
+    return MIFFT_OK;
+}
+
+int mifft_spectral_divergence(mifft_plan plan, const void* vx, const void* vy, const void* vz, void* d, void* ws,
+                              void* stream)
+{
+    clear_error();
+    int rc = check_spectral(plan, ws);
+    if (rc) return rc;
+    if ((rc = check_field(vx, "vx")) || (rc = check_field(vy, "vy")) || (rc = check_field(vz, "vz")) ||
+        (rc = check_field(d, "d")))
+        return rc;
+    if (d == vx || d == vy || d == vz) return set_error(MIFFT_ERR_INVALID, "d must not overlap the inputs");
+    const void* v[3] = {vx, vy, vz};
+    const std::vector<Pass>& P = plan->poisson;
+    const int mi = plan->poisson_mul;
+    const Pass& M = P[mi];
+    const BufId D = M.src;
+    char* w = (char*)(ws ? ws : plan->ws);
+    const size_t half = plan->poisson_ws_bytes / 2;
+    hipStream_t s = (hipStream_t)stream;
+    for (int j = 0; j < 3; ++j) {
+        std::vector<Pass> list(P.begin(), P.begin() + mi);
+        Pass m = M;
+        m.src = D;
+        m.dst = B_WS;
+        m.op = MIFFT_OP_DX + j;
+        m.acc = j > 0;
+        list.push_back(m);
+        if ((rc = run_passes(*plan, list, v[j], nullptr, w + 2 * half, w, w + half, s))) return rc;
+    }
+    std::vector<Pass> inv;
+    for (size_t k = mi + 1; k < P.size(); ++k) inv.push_back(renamed(P[k], D, B_WS));
+    return run_passes(*plan, inv, nullptr, d, w + 2 * half, w, w + half, s);
 }
 
 int mifft_execute_pencil_stages(mifft_plan plan, unsigned mask, void* a, void* send, void* recv,

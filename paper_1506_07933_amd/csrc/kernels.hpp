@@ -21,6 +21,7 @@
 #pragma once
 
 #include "fft_engine.hpp"
+#include "spectral.hpp"
 
 namespace mifft {
 
@@ -415,17 +416,20 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
     }
 }
 
-// ------------------------------------------- fused Poisson x-pass
-// The spectral Poisson solve's middle: on every x-line (fixed k1, k2) of the
-// half spectrum, the forward x-FFT, the multiplication by -scale / |k|^2
-// (0 at k = 0; signed k0, k1, non-negative k2; the same expression as the
-// standalone multiply) and the inverse x-FFT, with the line kept in LDS in
-// between: one read and one write of the spectrum instead of three of each.
-// Column col of group g is (k1, k2) = (g + col / nc, col % nc), which covers
-// both the transposed intermediate (groups = k1, columns = k2) and the
-// standard layout (one group, columns = k1 nc + k2).
+// ------------------------------------------- fused spectral x-pass
+// The middle of a spectral operator (Poisson solve, Laplacian, Helmholtz
+// solve, a partial derivative): on every x-line (fixed k1, k2) of the half
+// spectrum, the forward x-FFT, the multiplication by the operator's m(k)
+// (spectral_mul, the same expression as the standalone multiply) and the
+// inverse x-FFT, with the line kept in LDS in between: one read and one
+// write of the spectrum instead of three of each.  Column col of group g is
+// (k1, k2) = (g + col / nc, col % nc), which covers both the transposed
+// intermediate (groups = k1, columns = k2) and the standard layout (one
+// group, columns = k1 nc + k2).  src may equal data (in place); with acc the
+// result is added to what data holds (a sum of operators, e.g. divergence).
 template <typename T> struct PoissonXArgs {
-    cx<T>* data; // in place
+    const cx<T>* src;
+    cx<T>* data;
     const cx<T>* tw;
     int B;
     int log2B;
@@ -433,8 +437,9 @@ template <typename T> struct PoissonXArgs {
     int groups;
     int tpg; // as in StridedArgs
     long long gs, es;
-    int n1, nc;
-    T scale;
+    int n1, nc, n2;
+    int op, acc;
+    T scale, alpha;
 };
 
 // PHASE 0: the forward transform; the first stage reads global memory and
@@ -446,22 +451,25 @@ template <typename T> struct PoissonXArgs {
 template <typename T, int PHASE> struct PoissonCtx {
     using V = cx<T>;
     static constexpr bool kSyncAfterFirstRead = PHASE == 1; // the first stage reads the LDS tile
-    V* __restrict__ data;
+    const V* src;
+    V* data;
     V* lds; // column c of the tile: element idx at lds[idx * B]
     const V* twd;
     int t;
     int B;
     bool valid;
     long long es;
-    // PHASE 0
-    int n0;
-    long long kk12; // k1^2 + k2^2 of this column
-    T scale;
+    // PHASE 0: the multiplier
+    int n0, n1, n2, op;
+    long long i1, i2; // raw (k1, k2) indices of this column
+    T scale, alpha;
+    // PHASE 1
+    bool acc;
 
     __device__ __forceinline__ V gload(int idx) const
     {
         if constexpr (PHASE == 0)
-            return valid ? data[(long long)idx * es] : V{T(0), T(0)};
+            return valid ? src[(long long)idx * es] : V{T(0), T(0)};
         else
             return lds[idx * B];
     }
@@ -470,21 +478,19 @@ template <typename T, int PHASE> struct PoissonCtx {
     __device__ __forceinline__ void final_put(int idx, V v)
     {
         if constexpr (PHASE == 0) {
-            const long long k0 = (2 * idx < n0) ? idx : idx - n0;
-            const long long kk = k0 * k0 + kk12;
-            if (kk == 0) {
-                v = V{T(0), T(0)};
-            } else {
-                const T f = -scale / (T)kk;
-                v.x *= f;
-                v.y *= f;
-            }
+            v = spectral_mul<T>(op, idx, i1, i2, n0, n1, n2, scale, alpha, v);
             v.y = -v.y; // the inverse runs as conj(F(conj(.)))
             lds[idx * B] = v;
         } else {
             if (!valid) return;
             v.y = -v.y;
-            data[(long long)idx * es] = v;
+            V* p = data + (long long)idx * es;
+            if (acc) {
+                const V o = *p;
+                v.x += o.x;
+                v.y += o.y;
+            }
+            *p = v;
         }
     }
     __device__ __forceinline__ V tw(int e) const { return twd[e]; }
@@ -515,23 +521,27 @@ __global__ __launch_bounds__(1024) void k_strided_poisson(PoissonXArgs<T> a)
     const V* twd = stage_twiddles<T>(a.tw, L, smem + a.B * L);
     PoissonCtx<T, 0> c0;
     c0.valid = g < a.groups;
-    c0.data = a.data + (long long)g * a.gs + col;
+    const long long off = (long long)g * a.gs + col;
+    c0.src = a.src + off;
+    c0.data = a.data + off;
     c0.lds = smem + cc;
     c0.twd = twd;
     c0.t = t;
     c0.B = a.B;
     c0.es = a.es;
     c0.n0 = L;
-    {
-        const int k1i = g + col / a.nc, k2 = col % a.nc;
-        const long long k1 = (2 * k1i < a.n1) ? k1i : k1i - a.n1;
-        c0.kk12 = k1 * k1 + (long long)k2 * k2;
-    }
+    c0.n1 = a.n1;
+    c0.n2 = a.n2;
+    c0.op = a.op;
+    c0.i1 = g + col / a.nc;
+    c0.i2 = col % a.nc;
     c0.scale = a.scale;
+    c0.alpha = a.alpha;
     LineFFT<T, L, TPL, decltype(c0), RLt>::run(c0);
-    __syncthreads(); // the scaled spectrum of every column is in the tile
+    __syncthreads(); // the multiplied spectrum of every column is in the tile
     PoissonCtx<T, 1> c1;
     c1.valid = c0.valid;
+    c1.acc = a.acc != 0;
     c1.data = c0.data;
     c1.lds = c0.lds;
     c1.twd = twd;

@@ -349,6 +349,7 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
     }
     case P_POISSON_X: {
         PoissonXArgs<T> a;
+        a.src = (const V*)src;
         a.data = (V*)dst;
         a.tw = (const V*)p.tw;
         a.B = p.B;
@@ -360,7 +361,11 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.es = p.es_in;
         a.n1 = p.n1;
         a.nc = p.n2c;
+        a.n2 = p.nz;
+        a.op = p.op;
+        a.acc = p.acc;
         a.scale = (T)p.scale;
+        a.alpha = (T)p.alpha;
         ensure_lds(reinterpret_cast<const void*>(v.poisson_x), p.shmem);
         hipLaunchKernelGGL(v.poisson_x, dim3(p.grid), dim3(p.block), p.shmem, s, a);
         break;
@@ -385,7 +390,8 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         break;
     }
     case P_POISSON:
-        return launch_poisson<T>((V*)dst, p.n0, p.n1, p.n2c, (T)p.scale, s);
+        return launch_spectral<T>((const V*)src, (V*)dst, p.n0, p.n1, p.n2c, p.nz, p.op, (T)p.scale, (T)p.alpha,
+                                  p.acc, s);
     case P_PACK:
         return launch_pack<T>((const V*)src, (V*)dst, p.n0, p.n1, p.p1, p.M, s);
     case P_UNPACK:
@@ -974,7 +980,8 @@ int validate_extents(const Plan& plan)
 void rebuild_poisson(Plan& plan)
 {
     plan.poisson.clear();
-    plan.poisson_ws_bytes = 0;
+    plan.poisson_ws_bytes = plan.spectral_ws_bytes = 0;
+    plan.poisson_mul = -1;
     if (plan.kind != MIFFT_R2C) return;
     const int nc = plan.n2 / 2 + 1;
     const size_t half_bytes = (size_t)plan.n0 * plan.n1 * nc * plan.esz;
@@ -1028,6 +1035,7 @@ void rebuild_poisson(Plan& plan)
             x.n0 = plan.n0;
             x.n1 = plan.n1;
             x.n2c = pitch; // column -> (k1, k2) = (g + col / pitch, col % pitch)
+            x.nz = plan.n2;
             x.scale = scale;
             x.tag = 2;
             x.src = x.dst = D;
@@ -1052,8 +1060,10 @@ void rebuild_poisson(Plan& plan)
             zi.dst = B_OUT;
             plan.poisson.push_back(zi);
         }
+        plan.poisson_mul = (int)plan.poisson.size() - 1 - (plan.n1 > 1 ? 2 : 1);
         plan.poisson_ws_bytes = 2 * (size_t)plan.n0 * plan.n1 * pitch * plan.esz;
-        if (plan.poisson_ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.poisson_ws_bytes;
+        plan.spectral_ws_bytes = plan.poisson_ws_bytes / 2 * 3;
+        if (plan.spectral_ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.spectral_ws_bytes;
         return;
     fallback: // (only a failed twiddle allocation): the unfused solve
         plan.poisson.clear();
@@ -1068,8 +1078,10 @@ void rebuild_poisson(Plan& plan)
     m.n0 = plan.n0;
     m.n1 = plan.n1;
     m.n2c = nc;
+    m.nz = plan.n2;
     m.scale = scale;
     m.src = m.dst = B_SEND;
+    plan.poisson_mul = (int)plan.poisson.size();
     plan.poisson.push_back(m);
     for (Pass q : plan.inv) { // A -> ... -> OUT, workspace B
         q.src = remap(q.src, B_SEND, B_OUT, B_RECV);
@@ -1080,7 +1092,8 @@ void rebuild_poisson(Plan& plan)
     // transposed intermediate
     const size_t w_bytes = plan.transposed ? (size_t)plan.n0 * plan.n1 * plan.ncw * plan.esz : half_bytes;
     plan.poisson_ws_bytes = 2 * std::max(half_bytes, w_bytes);
-    if (plan.poisson_ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.poisson_ws_bytes;
+    plan.spectral_ws_bytes = plan.poisson_ws_bytes / 2 * 3;
+    if (plan.spectral_ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.spectral_ws_bytes;
 }
 
 int build_pencil(Plan& plan, unsigned /*flags*/)

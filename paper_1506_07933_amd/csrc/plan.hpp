@@ -53,6 +53,10 @@ struct Pass {
     long long blk = 0;
     // auxiliary kernels
     int n0 = 0, n1 = 0, n2c = 0, p1 = 0, M = 0;
+    // spectral multiply (P_POISSON, P_POISSON_X): operator, its parameter,
+    // the full z length (Nyquist index), and whether to add to the output
+    int op = 0, nz = 0, acc = 0;
+    double alpha = 0.0;
     size_t bytes = 0;
     double scale = 1.0;
     // byte offsets added to the resolved source / destination (chunked passes)
@@ -101,7 +105,9 @@ public:
     void* ws = nullptr;
     size_t ws_bytes = 0;         // workspace an execute call needs
     size_t default_ws_bytes = 0; // size of the plan's own workspace (covers Poisson too)
-    size_t poisson_ws_bytes = 0;
+    size_t poisson_ws_bytes = 0;  // two half-spectrum buffers (Poisson solve, one operator)
+    size_t spectral_ws_bytes = 0; // three (gradient, divergence)
+    int poisson_mul = -1;         // index of the multiply pass in `poisson`
     // opt-in per-pass event timing
     std::vector<hipEvent_t> prof_events; // max_calls * (max passes + 1)
     int prof_max_calls = 0, prof_calls = 0, prof_stride = 0, prof_npass = 0;

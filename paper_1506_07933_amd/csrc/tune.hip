@@ -76,8 +76,8 @@ static void save_wisdom_locked()
 
 static std::string pass_key(const Plan& plan, const Pass& p, const char* arch)
 {
-    static const char* kn[] = {"contig", "contig_pack", "strided", "strided_unpack", "r2c_z",
-                               "c2r_z",  "poisson",     "pack",    "unpack",         "copy", "poisson_x"};
+    static const char* kn[] = {"contig", "contig_pack", "strided", "strided_unpack", "r2c_z",    "c2r_z",
+                               "poisson", "pack",       "unpack",  "copy",           "poisson_x", "strided_pack"};
     std::ostringstream k;
     k << arch << "|" << (plan.prec == MIFFT_FP64 ? "fp64" : "fp32") << "|" << kn[p.kind] << "|L=" << p.L;
     if (p.kind == P_STRIDED || p.kind == P_STRIDED_SPLIT)

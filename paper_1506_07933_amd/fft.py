@@ -107,6 +107,23 @@ def poisson_solve(plan, f_ptr, u_ptr, ws_ptr=None, stream=None) -> None:
     check(lib.mifft_poisson_solve(plan, f_ptr, u_ptr, ws_ptr, stream), "mifft_poisson_solve")
 
 
+def spectral_apply(plan, op, alpha, f_ptr, u_ptr, ws_ptr=None, stream=None) -> None:
+    check(lib.mifft_spectral_apply(plan, op, float(alpha), f_ptr, u_ptr, ws_ptr, stream),
+          "mifft_spectral_apply")
+
+
+def spectral_gradient(plan, f_ptr, gx, gy, gz, ws_ptr=None, stream=None) -> None:
+    check(lib.mifft_spectral_gradient(plan, f_ptr, gx, gy, gz, ws_ptr, stream), "mifft_spectral_gradient")
+
+
+def spectral_divergence(plan, vx, vy, vz, d_ptr, ws_ptr=None, stream=None) -> None:
+    check(lib.mifft_spectral_divergence(plan, vx, vy, vz, d_ptr, ws_ptr, stream), "mifft_spectral_divergence")
+
+
+def spectral_ws_bytes(plan: int) -> int:
+    return int(lib.mifft_spectral_ws_bytes(plan))
+
+
 def workspace_bytes(plan: int) -> int:
     return int(lib.mifft_workspace_bytes(plan))
 
@@ -219,7 +236,52 @@ class Plan:
         self._check(f, self.shape, self.rdtype, "f")
         if out is None:
             out = torch.empty(self.shape, dtype=self.rdtype, device=f.device)
+        self._check(out, self.shape, self.rdtype, "out")
         poisson_solve(self.handle, _ptr(f), _ptr(out), _ptr(ws), _stream_handle(stream))
+        return out
+
+    @property
+    def spectral_ws_bytes(self) -> int:
+        return spectral_ws_bytes(self.handle)
+
+    def _ws(self, ws, need: int):
+        if ws is not None and ws.numel() * ws.element_size() < need:
+            raise ValueError("workspace of %d bytes is smaller than the %d needed"
+                             % (ws.numel() * ws.element_size(), need))
+        return _ptr(ws)
+
+    def spectral(self, op: int, f: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 alpha: float = 0.0, stream=None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """u = C2R(m(k) R2C(f)) / N for one of the MIFFT_OP_* operators."""
+        self._check(f, self.shape, self.rdtype, "f")
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.rdtype, device=f.device)
+        self._check(out, self.shape, self.rdtype, "out")
+        spectral_apply(self.handle, op, alpha, _ptr(f), _ptr(out), self._ws(ws, self.poisson_ws_bytes),
+                       _stream_handle(stream))
+        return out
+
+    def gradient(self, f: torch.Tensor, outs=None, stream=None, ws: Optional[torch.Tensor] = None):
+        """(df/dx, df/dy, df/dz) of a real periodic field."""
+        self._check(f, self.shape, self.rdtype, "f")
+        if outs is None:
+            outs = [torch.empty(self.shape, dtype=self.rdtype, device=f.device) for _ in range(3)]
+        for g in outs:
+            self._check(g, self.shape, self.rdtype, "gradient component")
+        spectral_gradient(self.handle, _ptr(f), *[_ptr(g) for g in outs],
+                          self._ws(ws, self.spectral_ws_bytes), _stream_handle(stream))
+        return outs
+
+    def divergence(self, v, out: Optional[torch.Tensor] = None, stream=None,
+                   ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """dv0/dx + dv1/dy + dv2/dz of three real periodic fields."""
+        for c in v:
+            self._check(c, self.shape, self.rdtype, "field component")
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.rdtype, device=v[0].device)
+        self._check(out, self.shape, self.rdtype, "out")
+        spectral_divergence(self.handle, *[_ptr(c) for c in v], _ptr(out),
+                            self._ws(ws, self.spectral_ws_bytes), _stream_handle(stream))
         return out
 
     def close(self) -> None:
@@ -374,5 +436,6 @@ class SlabPlan:
 __all__ = ["Plan", "PencilPlan", "SlabPlan", "MifftError", "plan_create", "plan_create_pencil",
            "plan_create_slab", "plan_create_nd", "execute_forward", "execute_inverse", "execute_forward_ws",
            "execute_inverse_ws", "execute_pencil_stages", "execute_slab_stages", "poisson_solve",
+           "spectral_apply", "spectral_gradient", "spectral_divergence", "spectral_ws_bytes",
            "workspace_bytes", "poisson_ws_bytes", "plan_destroy", "plan_describe",
            "profile_begin", "profile_end", "version"]

@@ -142,6 +142,11 @@ def test_stale_and_null_handles(L):
     assert L.mifft_execute_slab_stages(bogus, 1, buf, buf, buf, buf, None) == 5
     assert L.mifft_execute_slab_stages(None, 1, buf, buf, buf, buf, None) == 1
     assert L.mifft_poisson_solve(bogus, buf, buf, None, None) == 5
+    assert L.mifft_spectral_apply(bogus, 1, 0.0, buf, buf, None, None) == 5
+    assert L.mifft_spectral_apply(None, 1, 0.0, buf, buf, None, None) == 1
+    assert L.mifft_spectral_gradient(bogus, buf, buf, buf, buf, None, None) == 5
+    assert L.mifft_spectral_divergence(bogus, buf, buf, buf, buf, None, None) == 5
+    assert L.mifft_spectral_ws_bytes(bogus) == 0
     assert L.mifft_workspace_bytes(bogus) == 0
     s = ctypes.create_string_buffer(64)
     assert L.mifft_plan_describe(bogus, s, 64) == 5

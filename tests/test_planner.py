@@ -372,3 +372,15 @@ def test_nd_passes_stay_inside_the_buffers(dims):
             continue
         for prec in (0, 1):
             nd_only(dims, kind, prec)
+
+
+@pytest.mark.parametrize("shape", [(512, 512, 512), (64, 48, 32), (1, 32, 64)])
+def test_spectral_workspace_is_three_halves(shape):
+    """Gradient and divergence keep one spectrum while they build another:
+    three half-spectrum buffers, 1.5 x the Poisson workspace."""
+    h = ctypes.c_void_p()
+    assert lib.mifft_plan_create(ctypes.byref(h), *shape, 1, 0, MIFFT_PLAN_ONLY) == 0
+    pws = lib.mifft_poisson_ws_bytes(h.value)
+    sws = lib.mifft_spectral_ws_bytes(h.value)
+    plan_destroy(h.value)
+    assert pws > 0 and sws == pws // 2 * 3
