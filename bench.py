@@ -135,11 +135,38 @@ def nd_4d(torch, time_fn, warmup, steps):
             "inverse_in_place_ms": round(i, 4), "inverse_alg_GBps": round(64 * n / i / 1e6, 1)}
 
 
+def spectral_512(torch, np, time_fn, warmup, steps):
+    """Spectral operators on the 512^3 FP32 R2C plan (the Poisson right-hand
+    side recipe as input): Laplacian (five passes with the fused x-pass),
+    gradient (forward once, three fused multiplies and inverses) and
+    divergence (three forwards and fused multiplies, one inverse).
+    Algorithmic bytes, R = real field, H = half spectrum: Laplacian 2R + 8H,
+    gradient 4R + 18H, divergence 4R + 20H."""
+    from paper_1506_07933_amd import Plan, synth
+    from paper_1506_07933_amd._lib import MIFFT_OP_LAPLACIAN
+    n = 512
+    p = Plan((n, n, n), "r2c", "fp32")
+    f = synth.poisson_rhs_torch(n, 0, torch.float32, "cuda")
+    v = [synth.poisson_rhs_torch(n, s, torch.float32, "cuda") for s in (1, 2, 3)]
+    ws = torch.empty(p.spectral_ws_bytes, dtype=torch.uint8, device="cuda")
+    u = torch.empty_like(f)
+    g = [torch.empty_like(f) for _ in range(3)]
+    lap = time_fn(lambda: p.spectral(MIFFT_OP_LAPLACIAN, f, out=u, ws=ws), warmup, steps)
+    grad = time_fn(lambda: p.gradient(f, outs=g, ws=ws), warmup, steps)
+    div = time_fn(lambda: p.divergence(v, out=u, ws=ws), warmup, steps)
+    p.close()
+    R = 4.0 * n ** 3
+    H = 8.0 * n * n * (n // 2 + 1)
+    return {"laplacian_ms": round(lap, 4), "laplacian_alg_GBps": round((2 * R + 8 * H) / lap / 1e6, 1),
+            "gradient_ms": round(grad, 4), "gradient_alg_GBps": round((4 * R + 18 * H) / grad / 1e6, 1),
+            "divergence_ms": round(div, 4), "divergence_alg_GBps": round((4 * R + 20 * H) / div / 1e6, 1)}
+
+
 def workload_mode(args):
     """One secondary workload alone (for rocprofv3): the 64 uneven transforms
     in one persistent graph launch and as per-pass kernels, 512^3 R2C
-    Poisson solves (FP32 and FP64), one task's 512^3 slab share, or the 4-D
-    512 x 256 x 128 x 64 C2C transform."""
+    Poisson solves (FP32 and FP64), one task's 512^3 slab share, the 4-D
+    512 x 256 x 128 x 64 C2C transform, or the 512^3 spectral operators."""
     import numpy as np
     import torch
 
@@ -161,6 +188,8 @@ def workload_mode(args):
         out.update(slab_share(torch, np, time_fn, args.warmup, args.steps))
     elif args.mode == "nd":
         out.update(nd_4d(torch, time_fn, args.warmup, args.steps))
+    elif args.mode == "spectral":
+        out.update(spectral_512(torch, np, time_fn, args.warmup, args.steps))
     else:
         for prec, dt in (("fp32", np.float32), ("fp64", np.float64)):
             f, _ = synth.poisson_rhs(512, seed=0, dtype=dt)
@@ -231,6 +260,7 @@ def secondary(torch, np, steps):
     del a, send, ob
     out["slab_share_512cube_p4_fp32"] = slab_share(torch, np, time_fn, 2, steps)
     out["c2c_4d_512x256x128x64_fp32"] = nd_4d(torch, time_fn, 2, max(3, steps // 4))
+    out["spectral_512cube_fp32"] = spectral_512(torch, np, time_fn, 2, max(3, steps // 2))
     # 64 uneven transforms in one persistent graph launch vs per-pass kernels
     shapes, data = synth.batched_uneven(64, seed=0, dtype=np.complex64)
     xs = [torch.from_numpy(d).cuda() for d in data]
@@ -260,9 +290,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab", "nd"], default="fft",
+    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab", "nd", "spectral"], default="fft",
                     help="copy: plain 1 GiB device copy (counter scaling); batched / poisson / "
-                         "slab / nd: only that secondary workload, for profiling")
+                         "slab / nd / spectral: only that secondary workload, for profiling")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -271,7 +301,7 @@ def main():
         sys.exit(2)
     if args.mode == "copy":
         return copy_mode(args)
-    if args.mode in ("batched", "poisson", "slab", "nd"):
+    if args.mode in ("batched", "poisson", "slab", "nd", "spectral"):
         return workload_mode(args)
 
     import numpy as np
@@ -304,6 +334,17 @@ def main():
     wall = time.perf_counter() - t0
     pass_ms, ncalls = profile_end(plan.handle, max_passes=64)
     ms = start.elapsed_time(stop) / args.steps
+    # the same steps timed one by one (after the timed region), for the
+    # median and the minimum per step
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for i in range(args.steps):
+        plan.forward(x, out=y)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per_step = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
+    ms_median = per_step[len(per_step) // 2] if len(per_step) % 2 else \
+        0.5 * (per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2])
 
     # a plain device copy of the same 1 GiB, for context
     cpy = torch.empty_like(x)
@@ -343,6 +384,8 @@ def main():
         "device_copy_GBps": round(2 * 8 * n / (copy_ms * 1e-3) / 1e9, 1),
         "frac_of_device_copy": round(value / (2 * 8 * n / (copy_ms * 1e-3) / 1e9), 4),
         "wall_ms_per_step": round(wall * 1e3 / args.steps, 5),
+        "ms_per_step_median": round(ms_median, 5),
+        "ms_per_step_min": round(per_step[0], 5),
         "passes": [{"pass": names[a], "ms": round(per_axis[a], 5), "launches": axes.count(a),
                     "alg_GBps": round(kbytes / (per_axis[a] * 1e-3) / 1e9, 1)} for a in "zyx"
                    if a in per_axis],
