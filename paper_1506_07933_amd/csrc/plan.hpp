@@ -128,6 +128,7 @@ int variant_emul(int prec, int idx);
 int variant_prefetch(int prec, int idx);
 int find_variant(int prec, int L, int policy, int emul);
 int default_variant(int prec, int L);
+int contig_variant(int prec, int L);
 
 bool supported_length(int L);
 FastDiv make_fastdiv(uint32_t d);
