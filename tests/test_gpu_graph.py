@@ -79,3 +79,53 @@ def test_poisson_graph_transposed(prec):
     (ref,) = _replays_equal(run, [u])
     assert rel_l2(ref.cpu().numpy(), oracle.poisson_solve(f.cpu().numpy().astype(np.float64))) <= TOL[prec]
     p.close()
+
+
+def test_spectral_gradient_divergence_graph():
+    """Gradient and divergence (several launches over a caller workspace)
+    captured together and replayed."""
+    from paper_1506_07933_amd import Plan
+    shape = (64, 256, 256)
+    f = torch.from_numpy(synth.normal_real(shape, np.float32, seed=7)).cuda()
+    v = [torch.from_numpy(synth.normal_real(shape, np.float32, seed=8 + j)).cuda() for j in range(3)]
+    p = Plan(shape, "r2c", "fp32")
+    ws = torch.empty(p.spectral_ws_bytes, dtype=torch.uint8, device="cuda")
+    g = [torch.empty_like(f) for _ in range(3)]
+    d = torch.empty_like(f)
+
+    def run():
+        p.gradient(f, outs=g, ws=ws)
+        p.divergence(v, out=d, ws=ws)
+
+    ref = _replays_equal(run, g + [d])
+    want = oracle.gradient(f.cpu().numpy().astype(np.float64))
+    for j in range(3):
+        assert rel_l2(ref[j].cpu().numpy(), want[j]) <= TOL["fp32"]
+    p.close()
+
+
+def test_slab_and_nd_graph():
+    """One task's slab stages (p = 2, the send buffer as the receive buffer) and a rank-4 plan's
+    forward + inverse captured and replayed."""
+    from paper_1506_07933_amd import Plan, SlabPlan
+    sp = SlabPlan((32, 32, 32), 2, "c2c", "fp32")
+    a = torch.from_numpy(synth.uniform_complex(sp.slab_shape, np.complex64, seed=9)).cuda()
+    send = torch.empty(sp.send_shape, dtype=torch.complex64, device="cuda")
+    mid = torch.empty(sp.mid_shape, dtype=torch.complex64, device="cuda")
+    share = torch.empty(sp.share_shape, dtype=torch.complex64, device="cuda")
+    nd = Plan((8, 12, 16, 20), "c2c", "fp64")
+    x = torch.from_numpy(synth.uniform_complex((8, 12, 16, 20), np.complex128, seed=10)).cuda()
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+
+    def run():
+        sp.forward_local(a, send, mid)
+        sp.forward_x(send, share)  # the send buffer stands in for the received slab
+        nd.forward(x, out=y)
+        nd.inverse(y, out=z)
+
+    ref = _replays_equal(run, [send, share, y, z])
+    want = oracle.fftnd_c2c(x.cpu().numpy(), -1)
+    assert rel_l2(ref[2].cpu().numpy(), want) <= TOL["fp64"]
+    sp.close()
+    nd.close()
