@@ -183,8 +183,11 @@ def workload_mode(args):
         assert not bp.aborted()
         bk = BatchPlan(shapes, "fp32", mode="kernels")
         out["per_pass_kernels_ms"] = time_fn(lambda: bk.forward(xs, outs), args.warmup, args.steps)
+        bg = BatchPlan(shapes, "fp32", mode="grouped")
+        out["grouped_graph_ms"] = time_fn(lambda: bg.forward(xs, outs, graph=True), args.warmup, args.steps)
         bp.close()
         bk.close()
+        bg.close()
     elif args.mode == "slab":
         out.update(slab_share(torch, np, time_fn, args.warmup, args.steps))
     elif args.mode == "nd":
@@ -268,7 +271,8 @@ def secondary(torch, np, steps):
     out["slab_share_512cube_p4_fp32"] = slab_share(torch, np, time_fn, 2, steps)
     out["c2c_4d_512x256x128x64_fp32"] = nd_4d(torch, time_fn, 2, max(3, steps // 4))
     out["spectral_512cube_fp32"] = spectral_512(torch, np, time_fn, 2, max(3, steps // 2))
-    # 64 uneven transforms in one persistent graph launch vs per-pass kernels
+    # 64 uneven transforms: one persistent graph launch, per-pass kernels, and
+    # one launch per pass and shape (in a graph)
     shapes, data = synth.batched_uneven(64, seed=0, dtype=np.complex64)
     xs = [torch.from_numpy(d).cuda() for d in data]
     outs = [torch.empty_like(v) for v in xs]
@@ -278,10 +282,15 @@ def secondary(torch, np, steps):
     assert not bp.aborted()
     bk = BatchPlan(shapes, "fp32", mode="kernels")
     k = time_fn(lambda: bk.forward(xs, outs), 2, steps)
+    bg = BatchPlan(shapes, "fp32", mode="grouped")
+    gg = time_fn(lambda: bg.forward(xs, outs, graph=True), 2, steps)
     out["batched_64_uneven_fp32"] = {"persistent_graph_ms": round(g, 4), "per_pass_kernels_ms": round(k, 4),
-                                     "elements": nb, "persistent_alg_GBps": round(48 * nb / g / 1e6, 1)}
+                                     "grouped_graph_ms": round(gg, 4), "elements": nb,
+                                     "persistent_alg_GBps": round(48 * nb / g / 1e6, 1),
+                                     "grouped_alg_GBps": round(48 * nb / gg / 1e6, 1)}
     bp.close()
     bk.close()
+    bg.close()
     del xs, outs
     # served Poisson solves: a short open-loop replay
     s, recs, ex = serve.serve(n_requests=300, rate=200.0, seed=0, slots=4, budget_gb=32.0)

@@ -82,6 +82,10 @@ typedef enum {
 
 #define MIFFT_BATCH_KERNELS 4u /* batches: run the per-pass kernels of ordinary plans instead of
                                   the persistent kernel (any supported length) */
+#define MIFFT_BATCH_GROUPED 8u /* batches: as MIFFT_BATCH_KERNELS, but each pass of all the
+                                  transforms of one shape runs as one launch (up to 16
+                                  transforms per launch; plans needing a workspace run
+                                  per transform) */
 #define MIFFT_PLAN_ONLY 2u /* build the pass list without touching the device: the
                               plan can be described (mifft_plan_describe) and
                               destroyed, execute calls return MIFFT_ERR_BADPLAN */
@@ -301,7 +305,8 @@ int mifft_spectral_divergence(mifft_plan plan, const void* vx, const void* vy, c
  * y-passes, then all x-passes; a pass waits on a completion counter of the
  * previous pass of its transform).  Every axis length must be 2 .. 256 with
  * prime factors 2, 3, 5, unless MIFFT_BATCH_KERNELS asks for the per-pass
- * kernels of ordinary plans instead (then MIFFT_TUNE tunes those plans).
+ * kernels of ordinary plans instead, or MIFFT_BATCH_GROUPED for those kernels
+ * with one launch per pass and shape (then MIFFT_TUNE tunes those plans).
  * The batched local FFTs are the per-task work of Alg. 1 for many grids at
  * once; scheduling them as one launch is this library's own design.
  */

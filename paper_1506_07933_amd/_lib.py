@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmifft.so")
 
 MIFFT_C2C, MIFFT_R2C = 0, 1
 MIFFT_FP32, MIFFT_FP64 = 0, 1
-MIFFT_HEURISTIC, MIFFT_TUNE, MIFFT_PLAN_ONLY, MIFFT_BATCH_KERNELS = 0, 1, 2, 4
+MIFFT_HEURISTIC, MIFFT_TUNE, MIFFT_PLAN_ONLY, MIFFT_BATCH_KERNELS, MIFFT_BATCH_GROUPED = 0, 1, 2, 4, 8
 MIFFT_STAGE_Z, MIFFT_STAGE_PACK, MIFFT_STAGE_UNPACK, MIFFT_STAGE_Y = 1, 2, 4, 8
 MIFFT_SLAB_Z, MIFFT_SLAB_Y, MIFFT_SLAB_X, MIFFT_SLAB_PACK, MIFFT_SLAB_UNPACK = 1, 2, 4, 8, 16
 MIFFT_SLAB_INVERSE = 256

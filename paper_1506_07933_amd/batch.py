@@ -10,7 +10,8 @@ from typing import Optional, Sequence
 
 import torch
 
-from ._lib import MIFFT_BATCH_KERNELS, MIFFT_C2C, MIFFT_FP32, MIFFT_FP64, MIFFT_TUNE, check, lib
+from ._lib import (MIFFT_BATCH_GROUPED, MIFFT_BATCH_KERNELS, MIFFT_C2C, MIFFT_FP32, MIFFT_FP64,
+                   MIFFT_TUNE, check, lib)
 from .fft import _ptr, _stream_handle
 
 _PREC = {"fp32": MIFFT_FP32, "fp64": MIFFT_FP64}
@@ -22,14 +23,18 @@ class BatchPlan:
 
     mode "persistent": one persistent kernel for the whole batch (axis
     lengths 2..256 with factors 2, 3, 5); mode "kernels": the per-pass
-    kernels of ordinary plans (any supported length)."""
+    kernels of ordinary plans (any supported length); mode "grouped": those
+    kernels with each pass of all transforms of one shape as one launch."""
 
     def __init__(self, shapes: Sequence[Sequence[int]], prec: str = "fp32",
                  mode: str = "persistent", tune: bool = False):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.prec = prec
         dims = (ctypes.c_int * (3 * len(self.shapes)))(*[v for s in self.shapes for v in s])
-        flags = (MIFFT_BATCH_KERNELS if mode == "kernels" else 0) | (MIFFT_TUNE if tune else 0)
+        modes = {"persistent": 0, "kernels": MIFFT_BATCH_KERNELS, "grouped": MIFFT_BATCH_GROUPED}
+        if mode not in modes:
+            raise ValueError("mode must be one of %s" % sorted(modes))
+        flags = modes[mode] | (MIFFT_TUNE if tune else 0)
         h = ctypes.c_void_p()
         check(lib.mifft_batch_create(ctypes.byref(h), len(self.shapes), dims, MIFFT_C2C,
                                      _PREC[prec], flags), "mifft_batch_create")

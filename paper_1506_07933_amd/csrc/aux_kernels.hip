@@ -56,7 +56,7 @@ __global__ void k_spectral(const cx<T>* src, cx<T>* dst, int n0, int n1, int n2c
     const long long r = i / n2c;
     const int i1 = (int)(r % n1);
     const int i0 = (int)(r / n1);
-    cx<T> v = spectral_mul<T>(op, i0, i1, i2, n0, n1, n2, scale, alpha, src[i]);
+    cx<T> v = spectral_mul<T>(op, i0, n0, spectral_col<T>(op, i1, i2, n1, n2, scale), scale, alpha, src[i]);
     if (acc) {
         const cx<T> o = dst[i];
         v.x += o.x;

@@ -34,6 +34,7 @@ int mifft_plan_destroy(mifft_plan);
 struct mifft_batch_s {
     int count = 0, prec = MIFFT_FP32;
     bool kernels = false; // per-pass kernel launches instead of the persistent kernel
+    bool grouped = false; // kernels: each pass of all transforms of one shape as one launch
     std::vector<int> dims;
     // persistent path
     std::vector<mifft::BatchPass> passes;
@@ -105,11 +106,14 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
     if (count < 1) return set_error(MIFFT_ERR_INVALID, "count must be >= 1");
     if (kind != MIFFT_C2C && kind != MIFFT_R2C) return set_error(MIFFT_ERR_INVALID, "bad kind %d", kind);
     if (prec != MIFFT_FP32 && prec != MIFFT_FP64) return set_error(MIFFT_ERR_INVALID, "bad precision %d", prec);
-    if (flags & ~(unsigned)(MIFFT_TUNE | MIFFT_BATCH_KERNELS))
+    if (flags & ~(unsigned)(MIFFT_TUNE | MIFFT_BATCH_KERNELS | MIFFT_BATCH_GROUPED))
         return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if ((flags & MIFFT_BATCH_GROUPED) && (flags & MIFFT_BATCH_KERNELS))
+        return set_error(MIFFT_ERR_INVALID, "MIFFT_BATCH_GROUPED and MIFFT_BATCH_KERNELS exclude each other");
     if (kind != MIFFT_C2C) return set_error(MIFFT_ERR_UNSUPPORTED, "batches are C2C only");
     if (count > kBatchMax) return set_error(MIFFT_ERR_UNSUPPORTED, "at most %d transforms per batch", kBatchMax);
-    const bool kernels = flags & MIFFT_BATCH_KERNELS;
+    const bool grouped = flags & MIFFT_BATCH_GROUPED;
+    const bool kernels = (flags & MIFFT_BATCH_KERNELS) || grouped;
     for (int t = 0; t < count; ++t)
         for (int a = 0; a < 3; ++a) {
             const int L = dims[3 * t + a];
@@ -136,6 +140,7 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
     b->count = count;
     b->prec = prec;
     b->kernels = kernels;
+    b->grouped = grouped;
     b->dims.assign(dims, dims + 3 * count);
     const size_t esz = prec == MIFFT_FP64 ? 16 : 8;
 
@@ -289,8 +294,65 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
     return MIFFT_OK;
 }
 
+// Grouped: pass k of every shape's plan, for all transforms of that shape,
+// before pass k + 1 of any; up to kMaxGroup transforms per launch.  A plan
+// with a pass that is not a plain contiguous / strided pass on the caller's
+// buffers, or that needs a workspace (which the members would share), runs
+// per transform instead.
+static bool plan_groupable(const Plan& P)
+{
+    if (P.ws_bytes != 0) return false;
+    for (const Pass& q : P.fwd)
+        if ((q.kind != P_CONTIG && q.kind != P_STRIDED) || (q.src != B_IN && q.src != B_OUT) ||
+            (q.dst != B_IN && q.dst != B_OUT))
+            return false;
+    return true;
+}
+
+static int enqueue_grouped(mifft_batch b, void* const* in, void* const* out, hipStream_t s)
+{
+    size_t npass = 0;
+    for (const auto& kv : b->plans) npass = std::max(npass, plan_of(kv.second)->fwd.size());
+    for (size_t k = 0; k < npass; ++k) {
+        for (const auto& kv : b->plans) {
+            const Plan* P = plan_of(kv.second);
+            if (k >= P->fwd.size()) continue;
+            std::vector<int> members;
+            for (int t = 0; t < b->count; ++t)
+                if (std::equal(kv.first.begin(), kv.first.end(), b->dims.begin() + 3 * t)) members.push_back(t);
+            if (!plan_groupable(*P)) {
+                for (int t : members)
+                    if (k == 0) {
+                        int rc = mifft_execute_forward(kv.second, in[t], out[t], s);
+                        if (rc) return rc;
+                    }
+                continue;
+            }
+            const Pass& q = P->fwd[k];
+            for (size_t i = 0; i < members.size();) {
+                const int ng = (int)std::min<size_t>(kMaxGroup, members.size() - i);
+                const void* src[kMaxGroup];
+                void* dst[kMaxGroup];
+                for (int j = 0; j < ng; ++j) {
+                    const int t = members[i + j];
+                    src[j] = (q.src == B_IN ? (const char*)in[t] : (const char*)out[t]) + q.off_in;
+                    dst[j] = (q.dst == B_IN ? (char*)in[t] : (char*)out[t]) + q.off_out;
+                }
+                const hipError_t e = ng > 1 ? launch_pass_group(q, b->prec, ng, src, dst, s)
+                                            : launch_pass(q, b->prec, src[0], dst[0], s);
+                if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+                i += ng;
+            }
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    return MIFFT_OK;
+}
+
 static int enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t s)
 {
+    if (b->grouped) return enqueue_grouped(b, in, out, s);
     if (b->kernels) {
         for (int t = 0; t < b->count; ++t) {
             std::vector<int> key(b->dims.begin() + 3 * t, b->dims.begin() + 3 * t + 3);
@@ -411,7 +473,8 @@ int batch_describe(mifft_batch b, char* buf, size_t len)
     std::string s;
     char line[256];
     if (b->kernels) {
-        snprintf(line, sizeof(line), "mode=kernels transforms=%d shapes=%zu\n", b->count, b->plans.size());
+        snprintf(line, sizeof(line), "mode=%s transforms=%d shapes=%zu\n", b->grouped ? "grouped" : "kernels",
+                 b->count, b->plans.size());
         s += line;
     } else {
         snprintf(line, sizeof(line), "mode=persistent transforms=%d passes=%zu items=%d grid=%u block=%d lds=%zu\n",

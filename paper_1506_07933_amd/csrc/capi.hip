@@ -45,6 +45,10 @@ static bool is_live(const void* p)
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+namespace mifft {
+const Plan* plan_of(mifft_plan h) { return static_cast<const Plan*>(h); }
+} // namespace mifft
+
 static int check_device(int* dev)
 {
     int n = 0;

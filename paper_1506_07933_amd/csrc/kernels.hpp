@@ -273,12 +273,22 @@ __device__ __forceinline__ cx<T>* stage_twiddles(const cx<T>* __restrict__ tw, i
     return dst;
 }
 
+// Grouped launches: with gridDim.y > 1, blockIdx.y selects one of up to
+// kMaxGroup transforms of the same shape, each with its own buffers (a batch
+// runs each pass of all its transforms of one shape as one launch).
+constexpr int kMaxGroup = 16;
+template <typename T> struct GroupPtrs {
+    const cx<T>* in[kMaxGroup];
+    cx<T>* out[kMaxGroup];
+};
+
 // Line l of a batch sits at (l / ni) * s_o + (l % ni) * s_i on each side, so a
 // pass can read lines in one order and write them in another (the lines
 // themselves stay contiguous).
 template <typename T> struct ContigArgs {
     const cx<T>* in;
     cx<T>* out;
+    GroupPtrs<T> grp;
     const cx<T>* tw;
     int nlines;
     int lines_per_wg;
@@ -301,12 +311,18 @@ __global__ __launch_bounds__(1024) void k_contig(ContigArgs<T> a)
     const long long line = (long long)blockIdx.x * a.lines_per_wg + ln;
     ContigCtx<T, WL, OUT_PACK> c;
     c.valid = line < a.nlines;
+    const V* ain = a.in;
+    V* aout = a.out;
+    if (gridDim.y > 1) {
+        ain = a.grp.in[blockIdx.y];
+        aout = a.grp.out[blockIdx.y];
+    }
     const long long lo = line / a.ni, li = line - lo * a.ni;
-    c.in = a.in + lo * a.is_o + li * a.is_i;
+    c.in = ain + lo * a.is_o + li * a.is_i;
     if constexpr (OUT_PACK)
-        c.out = a.out + line * (long long)a.pm.d;
+        c.out = aout + line * (long long)a.pm.d;
     else
-        c.out = a.out + lo * a.os_o + li * a.os_i;
+        c.out = aout + lo * a.os_o + li * a.os_i;
     c.lds = smem + ln * lds_padded_len(L);
     c.twd = stage_twiddles<T>(a.tw, L, smem + a.lines_per_wg * lds_padded_len(L));
     c.t = tid - ln * TPL;
@@ -319,6 +335,7 @@ __global__ __launch_bounds__(1024) void k_contig(ContigArgs<T> a)
 template <typename T> struct StridedArgs {
     const cx<T>* in;
     cx<T>* out;
+    GroupPtrs<T> grp;
     const cx<T>* tw;
     int B;
     int log2B;
@@ -392,10 +409,16 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
         out_off = (long long)g * a.gs_out + col;
         return g < (unsigned)a.groups;
     };
+    const V* ain = a.in;
+    V* aout = a.out;
+    if (gridDim.y > 1) {
+        ain = a.grp.in[blockIdx.y];
+        aout = a.grp.out[blockIdx.y];
+    }
     long long io = 0, oo = 0;
     c.valid = locate(tile, io, oo);
-    c.in = a.in + io;
-    c.out = a.out + oo;
+    c.in = ain + io;
+    c.out = aout + oo;
     if constexpr (PF) c.template load_first<L, TPL, R0>(c.in, c.valid);
     for (;;) {
         // Hide the strides' loop invariance: hoisting the per-element address
@@ -405,14 +428,14 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
         c.has_next = next < ntiles;
         long long nio = 0, noo = 0;
         c.nvalid = c.has_next ? locate(next, nio, noo) : false;
-        c.nin = a.in + nio;
+        c.nin = ain + nio;
         LineFFT<T, L, TPL, decltype(c), RLt>::run(c);
         if (!c.has_next) break;
         __syncthreads(); // the next tile's first stage overwrites the LDS tile
         tile = next;
         c.valid = c.nvalid;
         c.in = c.nin;
-        c.out = a.out + noo;
+        c.out = aout + noo;
     }
 }
 
@@ -460,8 +483,8 @@ template <typename T, int PHASE> struct PoissonCtx {
     bool valid;
     long long es;
     // PHASE 0: the multiplier
-    int n0, n1, n2, op;
-    long long i1, i2; // raw (k1, k2) indices of this column
+    int n0, op;
+    SpectralCol<T> col; // this column's share of the multiplier
     T scale, alpha;
     // PHASE 1
     bool acc;
@@ -478,7 +501,7 @@ template <typename T, int PHASE> struct PoissonCtx {
     __device__ __forceinline__ void final_put(int idx, V v)
     {
         if constexpr (PHASE == 0) {
-            v = spectral_mul<T>(op, idx, i1, i2, n0, n1, n2, scale, alpha, v);
+            v = spectral_mul<T>(op, idx, n0, col, scale, alpha, v);
             v.y = -v.y; // the inverse runs as conj(F(conj(.)))
             lds[idx * B] = v;
         } else {
@@ -530,11 +553,8 @@ __global__ __launch_bounds__(1024) void k_strided_poisson(PoissonXArgs<T> a)
     c0.B = a.B;
     c0.es = a.es;
     c0.n0 = L;
-    c0.n1 = a.n1;
-    c0.n2 = a.n2;
     c0.op = a.op;
-    c0.i1 = g + col / a.nc;
-    c0.i2 = col % a.nc;
+    c0.col = spectral_col<T>(a.op, g + col / a.nc, col % a.nc, a.n1, a.n2, a.scale);
     c0.scale = a.scale;
     c0.alpha = a.alpha;
     LineFFT<T, L, TPL, decltype(c0), RLt>::run(c0);

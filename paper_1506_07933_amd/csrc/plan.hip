@@ -307,17 +307,24 @@ void strided_grid(const Plan& plan, Pass& p)
     if (ntiles > cap) p.grid = (unsigned)cap;
 }
 
+// ng > 1 (contiguous and strided passes): one launch over ng transforms of
+// the same shape, member i reading gsrc[i] and writing gdst[i] (blockIdx.y).
 template <typename T>
-static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStream_t s)
+static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStream_t s, int ng = 1,
+                             const void* const* gsrc = nullptr, void* const* gdst = nullptr)
 {
     const Variant<T>& v = table<T>()[p.vidx];
     using V = cx<T>;
     switch (p.kind) {
     case P_CONTIG:
     case P_CONTIG_PACK: {
-        ContigArgs<T> a;
+        ContigArgs<T> a{};
         a.in = (const V*)src;
         a.out = (V*)dst;
+        for (int i = 0; i < ng && ng > 1; ++i) {
+            a.grp.in[i] = (const V*)gsrc[i];
+            a.grp.out[i] = (V*)gdst[i];
+        }
         a.tw = (const V*)p.tw;
         a.nlines = (int)p.nlines;
         a.lines_per_wg = p.lines_per_wg;
@@ -331,15 +338,19 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.os_i = p.os_i;
         auto fn = p.kind == P_CONTIG ? v.contig : v.contig_pack;
         ensure_lds(reinterpret_cast<const void*>(fn), p.shmem);
-        hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.block), p.shmem, s, a);
+        hipLaunchKernelGGL(fn, dim3(p.grid, ng), dim3(p.block), p.shmem, s, a);
         break;
     }
     case P_STRIDED:
     case P_STRIDED_SPLIT:
     case P_STRIDED_OSPLIT: {
-        StridedArgs<T> a;
+        StridedArgs<T> a{};
         a.in = (const V*)src;
         a.out = (V*)dst;
+        for (int i = 0; i < ng && ng > 1; ++i) {
+            a.grp.in[i] = (const V*)gsrc[i];
+            a.grp.out[i] = (V*)gdst[i];
+        }
         a.tw = (const V*)p.tw;
         a.B = p.B;
         a.log2B = p.log2B;
@@ -358,7 +369,10 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
                   : p.kind == P_STRIDED_SPLIT ? v.strided_split
                                               : v.strided_osplit;
         ensure_lds(reinterpret_cast<const void*>(fn), p.shmem);
-        hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.block), p.shmem, s, a);
+        // a grid capped at the resident capacity is shared by the members
+        unsigned gx = p.grid;
+        if (ng > 1 && (int)p.grid < p.ntiles) gx = std::max(1u, (p.grid + (unsigned)ng - 1) / (unsigned)ng);
+        hipLaunchKernelGGL(fn, dim3(gx, ng), dim3(p.block), p.shmem, s, a);
         break;
     }
     case P_POISSON_X: {
@@ -414,6 +428,14 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         return launch_copy(src, dst, p.bytes, s);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_pass_group(const Pass& p, int prec, int ng, const void* const* src, void* const* dst,
+                             hipStream_t s)
+{
+    if (ng < 1 || ng > kMaxGroup || (p.kind != P_CONTIG && p.kind != P_STRIDED)) return hipErrorInvalidValue;
+    if (prec == MIFFT_FP64) return launch_fft<double>(p, src[0], dst[0], s, ng, src, dst);
+    return launch_fft<float>(p, src[0], dst[0], s, ng, src, dst);
 }
 
 hipError_t launch_pass(const Pass& p, int prec, const void* src, void* dst, hipStream_t s)

@@ -158,6 +158,12 @@ void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int group
 
 // Enqueue one pass with resolved buffers.
 hipError_t launch_pass(const Pass& p, int prec, const void* src, void* dst, hipStream_t s);
+// The same contiguous or strided pass of ng <= kMaxGroup transforms of one
+// shape as one launch (member i: src[i] -> dst[i]).
+hipError_t launch_pass_group(const Pass& p, int prec, int ng, const void* const* src, void* const* dst,
+                             hipStream_t s);
+// The plan behind a C-ABI handle (no liveness check).
+const Plan* plan_of(mifft_plan h);
 
 // Generate (or reuse) the twiddle table of length L on the current device.
 int get_twiddles(Plan& plan, int L, void** out);

@@ -56,8 +56,11 @@ def test_nd_c2c(shape, prec):
     p.close()
 
 
+# (8, 64, 32, 64) and (6, 40, 24, 48, 10): axis 0's stride is >= 256 KiB, so they run the
+# transposed intermediate (and the R2C inverse's two workspace spectra)
 R2C = [((8, 12, 10, 16), "fp32"), ((5, 4, 3, 6), "fp64"), ((3, 2, 2, 2, 2), "fp32"),
-       ((2, 3, 4, 5, 6, 8), "fp64"), ((32, 16, 8, 64), "fp32"), ((40,), "fp64"), ((12, 30), "fp32")]
+       ((2, 3, 4, 5, 6, 8), "fp64"), ((32, 16, 8, 64), "fp32"), ((40,), "fp64"), ((12, 30), "fp32"),
+       ((8, 64, 32, 64), "fp32"), ((8, 64, 32, 64), "fp64"), ((6, 40, 24, 48, 10), "fp64")]
 
 
 @pytest.mark.parametrize("shape,prec", R2C)
