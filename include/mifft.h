@@ -361,6 +361,12 @@ int mifft_profile_end(mifft_plan plan, float* avg_ms, int max_passes, int* npass
 /* Version string of the library build. */
 const char* mifft_version(void);
 
+/* One line per compiled kernel variant of a precision -- the autotuner's
+ * search space: "L=<length> policy=<radix order> emul=<radix groups per
+ * thread> tpl=<threads per line> radix=<r1>x<r2>x..." (stage order).  Needs
+ * no device.  INVALID if buf is NULL or shorter than the text. */
+int mifft_variants_describe(int prec, char* buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

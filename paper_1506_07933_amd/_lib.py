@@ -56,6 +56,7 @@ SIGNATURES = {
     "mifft_profile_end": (_i, [_vp, ctypes.POINTER(ctypes.c_float), _i,
                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "mifft_version": (ctypes.c_char_p, []),
+    "mifft_variants_describe": (_i, [_i, ctypes.c_char_p, _sz]),
 }
 
 

@@ -771,6 +771,27 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
 
 const char* mifft_version(void) { return "mifft 0.1 (gfx950)"; }
 
+int mifft_variants_describe(int prec, char* buf, size_t len)
+{
+    clear_error();
+    if (!buf || len == 0) return set_error(MIFFT_ERR_INVALID, "NULL argument");
+    if (prec != MIFFT_FP32 && prec != MIFFT_FP64) return set_error(MIFFT_ERR_INVALID, "bad precision %d", prec);
+    std::string s;
+    for (int i = 0; i < variant_count(prec); ++i) {
+        int r[32];
+        const int n = variant_radices(prec, i, r, 32);
+        char line[256];
+        int o = snprintf(line, sizeof(line), "L=%d policy=%d emul=%d tpl=%d radix=", variant_L(prec, i),
+                         variant_policy(prec, i), variant_emul(prec, i), variant_tpl(prec, i));
+        for (int k = 0; k < n && o < (int)sizeof(line) - 8; ++k) o += snprintf(line + o, sizeof(line) - o, k ? "x%d" : "%d", r[k]);
+        s += line;
+        s += "\n";
+    }
+    if (s.size() + 1 > len) return set_error(MIFFT_ERR_INVALID, "buffer of %zu bytes holds less than %zu", len, s.size() + 1);
+    memcpy(buf, s.c_str(), s.size() + 1);
+    return MIFFT_OK;
+}
+
 int mifft_batch_create(mifft_batch* out, int count, const int* dims, int kind, int prec, unsigned flags)
 {
     clear_error();

@@ -118,6 +118,15 @@ int variant_prefetch(int prec, int i)
     return with_table(prec, [i](const auto& t) { return t[i].prefetch; });
 }
 
+int variant_radices(int prec, int i, int* radix, int max)
+{
+    return with_table(prec, [&](const auto& t) {
+        const int n = t[i].nstages;
+        for (int k = 0; k < n && k < max; ++k) radix[k] = t[i].radix[k];
+        return n;
+    });
+}
+
 int find_variant(int prec, int L, int policy, int emul)
 {
     return with_table(prec, [&](const auto& t) {

@@ -126,6 +126,7 @@ int variant_tpl(int prec, int idx);
 int variant_policy(int prec, int idx);
 int variant_emul(int prec, int idx);
 int variant_prefetch(int prec, int idx);
+int variant_radices(int prec, int idx, int* radix, int max); // stage count; radices in stage order
 int find_variant(int prec, int L, int policy, int emul);
 int default_variant(int prec, int L);
 int contig_variant(int prec, int L);
