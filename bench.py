@@ -242,6 +242,13 @@ def secondary(torch, np, steps):
     out["c2c_512cube_fp64_forward"] = {"ms": round(ms, 4), "alg_GBps": round(48 * 2 * 512 ** 3 / ms / 1e6, 1)}
     p.close()
     del x, y
+    # 32^3 complex128 forward + inverse (latency-bound)
+    x = torch.from_numpy(synth.uniform_complex((32, 32, 32), np.complex128, seed=0)).cuda()
+    y = torch.empty_like(x)
+    p = Plan((32, 32, 32), "c2c", "fp64")
+    ms = time_fn(lambda: (p.forward(x, out=y), p.inverse(y, out=y)), 5, max(10, steps))
+    out["c2c_32cube_fp64_forward_inverse"] = {"us": round(ms * 1e3, 2)}
+    p.close()
     # 256^3 R2C / C2R, FP64 and FP32
     for prec, rd, cd in (("fp64", np.float64, torch.complex128), ("fp32", np.float32, torch.complex64)):
         xr = torch.from_numpy(synth.normal_real((256, 256, 256), rd, seed=0)).cuda()
