@@ -162,6 +162,43 @@ def spectral_512(torch, np, time_fn, warmup, steps):
             "divergence_ms": round(div, 4), "divergence_alg_GBps": round((4 * R + 20 * H) / div / 1e6, 1)}
 
 
+def cpu_baseline_configs(np, reps=3):
+    """The oracle (unchanged) timed on the host's cores for the other
+    workloads, median of `reps` runs on the same input, FP64, as context beside
+    the GPU times: 32^3 C2C forward + inverse; 256^3 R2C forward; one pencil
+    share 256 x 256 x 1024 (z-DFT, pack, loopback, unpack, y-DFT); the 64
+    uneven transforms; one Poisson solve per served size (one run for 384^3
+    and 512^3)."""
+    import statistics
+    import oracle
+    from paper_1506_07933_amd import synth
+
+    def med(fn, n=reps):
+        ts = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        print("oracle: %.1f ms" % (statistics.median(ts) * 1e3), file=sys.stderr, flush=True)
+        return round(statistics.median(ts) * 1e3, 2)
+
+    out = {"cores": oracle.max_threads(), "unit": "ms", "reps": reps}
+    x = synth.uniform_complex((32, 32, 32), np.complex128, seed=0)
+    out["c2c_32cube_fwd_inv"] = med(lambda: oracle.fft3d_c2c(oracle.fft3d_c2c(x, -1), +1))
+    r = synth.normal_real((256, 256, 256), np.float64, seed=0)
+    out["r2c_256cube_fwd"] = med(lambda: oracle.fft3d_r2c(r))
+    a = synth.uniform_complex((256, 256, 1024), np.complex128, seed=0)
+    out["pencil_share_256x256x1024"] = med(lambda: oracle.pencil_share_forward(a, 4))
+    del a
+    shapes, data = synth.batched_uneven(64, seed=0, dtype=np.complex128)
+    out["batched_64_uneven"] = med(lambda: [oracle.fft3d_c2c(d, -1) for d in data])
+    del data
+    for n in (64, 128, 256, 384, 512):
+        f, _ = synth.poisson_rhs(n, seed=0)
+        out["poisson_%dcube" % n] = med(lambda: oracle.poisson_solve(f), reps if n < 384 else 1)
+    return out
+
+
 def workload_mode(args):
     """One secondary workload alone (for rocprofv3): the 64 uneven transforms
     in one persistent graph launch and as per-pass kernels, 512^3 R2C
@@ -194,6 +231,8 @@ def workload_mode(args):
         out.update(nd_4d(torch, time_fn, args.warmup, args.steps))
     elif args.mode == "spectral":
         out.update(spectral_512(torch, np, time_fn, args.warmup, args.steps))
+    elif args.mode == "oracle":
+        out.update(cpu_baseline_configs(np))
     elif args.mode == "serve":
         # the full served-Poisson replay: 2000 requests at 200 req/s (about 10 s)
         from paper_1506_07933_amd import serve
@@ -313,10 +352,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab", "nd", "spectral", "serve"], default="fft",
+    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab", "nd", "spectral", "serve", "oracle"], default="fft",
                     help="copy: plain 1 GiB device copy (counter scaling); batched / poisson / "
                          "slab / nd / spectral / serve: only that secondary workload (serve: the "
-                         "full 2000-request replay)")
+                         "full 2000-request replay); oracle: the CPU oracle's times for those "
+                         "workloads")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -325,7 +365,7 @@ def main():
         sys.exit(2)
     if args.mode == "copy":
         return copy_mode(args)
-    if args.mode in ("batched", "poisson", "slab", "nd", "spectral", "serve"):
+    if args.mode in ("batched", "poisson", "slab", "nd", "spectral", "serve", "oracle"):
         return workload_mode(args)
 
     import numpy as np
