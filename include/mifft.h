@@ -362,9 +362,11 @@ int mifft_profile_end(mifft_plan plan, float* avg_ms, int max_passes, int* npass
 const char* mifft_version(void);
 
 /* One line per compiled kernel variant of a precision -- the autotuner's
- * search space: "L=<length> policy=<radix order> emul=<radix groups per
- * thread> tpl=<threads per line> radix=<r1>x<r2>x..." (stage order).  Needs
- * no device.  INVALID if buf is NULL or shorter than the text. */
+ * search space (the candidates MIFFT_TUNE times, in the spirit of the MEASURE
+ * planning of Sec. 3): "L=<length> policy=<radix order> emul=<radix groups
+ * per thread> tpl=<threads per line> radix=<r1>x<r2>x..." (stage order).
+ * Needs no device.  INVALID if buf is NULL, shorter than the text, or prec
+ * is not MIFFT_FP32 / MIFFT_FP64. */
 int mifft_variants_describe(int prec, char* buf, size_t len);
 
 #ifdef __cplusplus
