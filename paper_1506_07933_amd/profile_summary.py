@@ -1,8 +1,8 @@
 """Summarise rocprofv3 output of bench.py runs into profiles/.
 
     python -m paper_1506_07933_amd.profile_summary \
-        --trace gpurun_out/trace --fetch gpurun_out/pmc_fetch --write gpurun_out/pmc_write \
-        --copy-fetch gpurun_out/pmc_copy_fetch --copy-write gpurun_out/pmc_copy_write \
+        --trace out/trace --fetch out/pmc_fetch --write out/pmc_write \
+        --copy-fetch out/pmc_copy_fetch --copy-write out/pmc_copy_write \
         --passes z_contig,y_strided,x_strided --title "..." --command "..." --out profiles/x.md
 
 The kernel trace gives per-dispatch durations; dispatches of the transform's
