@@ -34,7 +34,7 @@ def run_batch(shapes, data, prec, mode="persistent", graph=False, reps=1):
     return results
 
 
-def test_cfg4_batched_uneven_64_persistent():
+def test_batched_uneven_64_persistent():
     """64 transforms drawn by seed from {48^3, 64^3, 96^3, 128^3, 100x120x144,
     125^3}, complex64 N(0,1): one persistent launch; each transform against
     the oracle and against its single-plan GPU result."""
@@ -51,7 +51,7 @@ def test_cfg4_batched_uneven_64_persistent():
             plans[s] = Plan(s, "c2c", "fp32")
         single = plans[s].forward(torch.from_numpy(d).to(DEV)).cpu().numpy()
         assert rel_l2(r, single) <= 5e-6, (i, s)
-    print("  cfg4 64 transforms, worst rel_l2 vs oracle %.3e" % worst, flush=True)
+    print("  64 uneven transforms, worst rel_l2 vs oracle %.3e" % worst, flush=True)
 
 
 def test_batch_graph_replays_match_eager():

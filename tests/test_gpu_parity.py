@@ -47,21 +47,21 @@ def report(name, err, tol):
 
 # ---------------------------------------------------------------- C2C
 
-def test_cfg1_c2c_complex128_32cube():
+def test_c2c_complex128_32cube():
     """32^3 complex128, U[-1,1) seed 0: forward + inverse vs oracle and brute force."""
     from paper_1506_07933_amd import Plan
     x = synth.uniform_complex((32, 32, 32), np.complex128, seed=0)
     p = Plan(x.shape, "c2c", "fp64")
     X = host(p.forward(gpu(x)))
     ref = oracle.fft3d_c2c(x, -1)
-    report("cfg1 forward vs oracle", rel_l2(X, ref), 1e-13)
+    report("32^3 c128 forward vs oracle", rel_l2(X, ref), 1e-13)
     rng = np.random.default_rng(1)
     ks = np.stack([rng.integers(0, 32, 300) for _ in range(3)], axis=1)
-    report("cfg1 forward vs brute force (300 samples)",
+    report("32^3 c128 forward vs brute force (300 samples)",
            rel_l2(X[ks[:, 0], ks[:, 1], ks[:, 2]], brute_dft3_at(x, ks, -1)), 1e-13)
     xi = host(p.inverse(gpu(X)))
-    report("cfg1 inverse vs oracle", rel_l2(xi, oracle.fft3d_c2c(X, +1)), 1e-13)
-    report("cfg1 inverse(forward(x)) vs N x", rel_l2(xi, 32 ** 3 * x), 1e-13)
+    report("32^3 c128 inverse vs oracle", rel_l2(xi, oracle.fft3d_c2c(X, +1)), 1e-13)
+    report("32^3 c128 inverse(forward(x)) vs N x", rel_l2(xi, 32 ** 3 * x), 1e-13)
     p.close()
 
 
@@ -189,7 +189,7 @@ def test_nondefault_stream():
 # ------------------------------------------------------------ R2C / C2R
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_cfg2_r2c_c2r_256cube(prec):
+def test_r2c_c2r_256cube(prec):
     """256^3 real N(0,1): R2C to 256x256x129, C2R back (x N)."""
     from paper_1506_07933_amd import Plan
     x = synth.normal_real((256, 256, 256), RDT[prec], seed=0)
@@ -199,10 +199,10 @@ def test_cfg2_r2c_c2r_256cube(prec):
     assert tuple(Y.shape) == (256, 256, 129)
     Yh = host(Y)
     x64 = x.astype(np.float64)
-    report("cfg2 r2c %s" % prec, rel_l2(Yh, oracle.fft3d_r2c(x64)), TOL[prec])
+    report("256^3 r2c %s" % prec, rel_l2(Yh, oracle.fft3d_r2c(x64)), TOL[prec])
     xr = host(p.inverse(Y))
     np.testing.assert_array_equal(host(Y), Yh)     # C2R preserves its input
-    report("cfg2 c2r(r2c(x)) %s" % prec, rel_l2(xr, 256 ** 3 * x64), TOL[prec])
+    report("256^3 c2r(r2c(x)) %s" % prec, rel_l2(xr, 256 ** 3 * x64), TOL[prec])
     p.close()
 
 
@@ -291,7 +291,7 @@ def test_poisson_fused_x_matches_unfused(monkeypatch, prec, shape):
 
 # --------------------------------------------------------- pencil share
 
-def test_cfg3_pencil_share_fused_and_unfused():
+def test_pencil_share_256x256x1024_fused_and_unfused():
     """One rank's share of a 1024^3 C2C transform on a 4x4 grid: local
     256x256x1024 complex64; z-FFT, pack, loopback, unpack, y-FFT."""
     from paper_1506_07933_amd import PencilPlan
@@ -303,12 +303,12 @@ def test_cfg3_pencil_share_fused_and_unfused():
     out = torch.empty(pp.out_shape, dtype=torch.complex64, device=DEV)
     pp.forward_share(ad, send, out, fused=True)
     fused = host(out)
-    report("cfg3 fused share vs oracle", rel_l2(fused, ref), 5e-6)
+    report("pencil share fused vs oracle", rel_l2(fused, ref), 5e-6)
     np.testing.assert_array_equal(host(ad), a)     # fused z+pack leaves A alone
     out2 = torch.empty_like(out)
     pp.forward_share(ad, send, out2, fused=False)
     unfused = host(out2)
-    report("cfg3 unfused share vs oracle", rel_l2(unfused, ref), 5e-6)
+    report("pencil share unfused vs oracle", rel_l2(unfused, ref), 5e-6)
     np.testing.assert_array_equal(fused, unfused)  # same kernels' arithmetic, same bits
     pp.close()
 

@@ -54,7 +54,7 @@ def test_brute_force_full(shape, sign):
 
 @pytest.mark.parametrize("shape", [(32, 32, 32), (100, 12, 9), (5, 8, 125)])
 def test_brute_force_sampled(shape):
-    """cfg-1 size (32^3) and radix-5 heavy shapes, at 200 sampled outputs."""
+    """32^3 and radix-5 heavy shapes, at 200 sampled outputs."""
     x = _rand_c(shape, seed=3)
     got = oracle.fft3d_c2c(x, -1)
     rng = np.random.default_rng(7)
