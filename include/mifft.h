@@ -94,10 +94,10 @@ typedef enum {
 #define MIFFT_MAX_AXIS 1024
 
 /* Pencil stage bits for mifft_execute_pencil_stages. */
-#define MIFFT_STAGE_Z 1u      /* batched z-FFT of the local share (Algorithm 1, step 1) */
+#define MIFFT_STAGE_Z 1u      /* batched z-FFT of the local share (Algorithm 1) */
 #define MIFFT_STAGE_PACK 2u   /* pack into the row all-to-all send layout (Sec. 2) */
 #define MIFFT_STAGE_UNPACK 4u /* unpack the receive layout (Sec. 2) */
-#define MIFFT_STAGE_Y 8u      /* batched y-FFT (Algorithm 1, step 3) */
+#define MIFFT_STAGE_Y 8u      /* batched y-FFT (Algorithm 1) */
 
 /*
  * mifft_plan_create -- plan a 3-D transform of an n0 x n1 x n2 grid.
@@ -175,7 +175,7 @@ int mifft_plan_create_nd(mifft_plan* out, int rank, const int* dims, int kind, i
 /*
  * mifft_plan_create_pencil -- plan one rank's share of the pencil-decomposed
  * forward transform of an N0 x N1 x N2 C2C grid on a p0 x p1 process grid
- * (Sec. 2, pencil paragraph; Algorithm 1, steps 1-3).  The share is the
+ * (Sec. 2, pencil paragraph; Algorithm 1, up to the y-FFT).  The share is the
  * local array A[N0/p0][N1/p1][N2]; with M = N2/p1 the stages compute
  *   Z:      Ahat = z-FFT of A along its last axis (length N2)
  *   PACK:   S[j][i0][i1][m] = Ahat[i0][i1][j*M + m]   (send block j -> row peer j)

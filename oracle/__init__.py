@@ -13,7 +13,7 @@ Contents
     periodic solve -1/|k|^2 with the k = 0 mode zeroed).
   * ``pencil_pack / pencil_unpack / pencil_share_forward`` -- the pack, loopback
     exchange and unpack maps of the row all-to-all (Sec. 2, pencil paragraph,
-    and Algorithm 1, steps 1-3), written as numpy permutations.
+    and Algorithm 1 up to the y-FFT), written as numpy permutations.
   * ``slab_pack / slab_forward / slab_inverse`` -- the slab decomposition of
     Algorithm 3 for all tasks at once, the all-to-all done as array copies;
     ``c2r_z`` is the z-only C2R its inverse ends with.
@@ -184,7 +184,7 @@ def poisson_solve(f) -> np.ndarray:
     return fft3d_c2r(uh, n2) / n
 
 
-# ---- pencil share: pack, loopback exchange, unpack (Algorithm 1, steps 1-3) ----
+# ---- pencil share: pack, loopback exchange, unpack (Algorithm 1, up to the y-FFT) ----
 
 def pencil_pack(ahat, p1: int) -> np.ndarray:
     """Row all-to-all send layout S[j][i0][i1][m] = Ahat[i0][i1][j*M + m] with
@@ -224,7 +224,7 @@ def pencil_share_forward(a, p1: int) -> np.ndarray:
 def slab_pack(ahat, p: int) -> np.ndarray:
     """Send layout of the forward slab transpose: S[j][i0][i1][k2] =
     Ahat[i0][j*n1l + i1][k2] with n1l = N1/p, so block j holds the y range
-    that task j owns after the exchange (Algorithm 3, step T)."""
+    that task j owns after the exchange (the transpose of Algorithm 3)."""
     a = np.asarray(ahat)
     n0l, n1, nc = a.shape
     if n1 % p:

@@ -1,11 +1,11 @@
 // kernels.hpp -- the HIP kernels of the local FFT passes (templates).
 //
 // k_contig   batched 1-D FFTs along the contiguous axis (the z-pass,
-//            Algorithm 1 step 1), several lines per workgroup.  With
+//            Algorithm 1), several lines per workgroup.  With
 //            OUT_PACK the stores go straight to the row all-to-all send
 //            layout S[j][i0][i1][m] (Sec. 2: pack before the exchange).
 // k_strided  batched 1-D FFTs along a strided axis (the y- and x-passes,
-//            Algorithm 1 steps 3 and 5).  A workgroup owns a tile of B
+//            Algorithm 1).  A workgroup owns a tile of B
 //            adjacent columns, so every global access of a line element is a
 //            run of B contiguous complex values.  With SPLIT = 1 the loads
 //            follow the unpack map of the receive layout (Sec. 2: unpack after

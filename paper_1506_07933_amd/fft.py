@@ -297,8 +297,8 @@ class Plan:
 
 
 class PencilPlan:
-    """One rank's share of the pencil forward transform (Algorithm 1, steps
-    1-3) of an (N0, N1, N2) C2C grid on a p0 x p1 process grid."""
+    """One rank's share of the pencil forward transform (Algorithm 1, up to
+    the y-FFT) of an (N0, N1, N2) C2C grid on a p0 x p1 process grid."""
 
     def __init__(self, shape: Sequence[int], grid: Sequence[int], prec: str = "fp32"):
         self.shape = tuple(int(s) for s in shape)
