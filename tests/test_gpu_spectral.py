@@ -21,7 +21,7 @@ OPS = [oracle.OP_POISSON, oracle.OP_LAPLACIAN, oracle.OP_HELMHOLTZ, oracle.OP_DX
 # (shape, layout): 64 x 256 x 256 uses the transposed intermediate (x-stride
 # 256 x 129 x 8 bytes >= 256 KiB), the others the standard layout; n0 = 1 runs
 # the standalone multiply
-SHAPES = [(64, 256, 256), (32, 24, 40), (27, 25, 30), (1, 32, 64)]
+SHAPES = [(64, 256, 256), (32, 24, 40), (27, 25, 30), (1, 32, 64), (16, 1, 24)]  # n1 = 1: no y-pass
 
 
 def gpu(a):
