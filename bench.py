@@ -458,7 +458,10 @@ def main():
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_axis_pass": kbytes, "launches_per_step": launches,
-                     "steps_timed": ncalls},
+                     "steps_timed": ncalls,
+                     # counter bytes over the same measured launch duration (DRAM rate)
+                     "traffic_GBps": (round(traffic * launches / (per_axis[dom] * 1e-3) / 1e9, 1)
+                                      if traffic else None)},
     }
     if not args.no_cpu_baseline:
         import oracle
