@@ -199,6 +199,31 @@ def cpu_baseline_configs(np, reps=3):
     return out
 
 
+def pattern_mode(torch, time_fn, warmup, steps):
+    """Copy rates of the strided passes' access pattern with no arithmetic
+    (mifft_pattern_copy): the 512^3 y- and x-pass geometry -- 512 groups of
+    512 columns, rows read 4 KiB apart and written 2 MiB apart (the
+    transposing schedule) -- for several tile shapes, next to a plain
+    contiguous device copy.  The ceiling the strided FFT passes are read
+    against."""
+    from paper_1506_07933_amd._lib import check, lib
+    n = 512 ** 3
+    a = torch.empty(n, dtype=torch.complex64, device="cuda")
+    a.real.uniform_()
+    b = torch.empty_like(a)
+    out = {}
+    for B, T in ((32, 32), (32, 16), (64, 16), (16, 64), (128, 8)):
+        def run():
+            check(lib.mifft_pattern_copy(0, a.data_ptr(), b.data_ptr(), 512, 512, 512, 512, 512 * 512,
+                                         512 * 512, 512, B, T, torch.cuda.current_stream().cuda_stream),
+                  "mifft_pattern_copy")
+        ms = time_fn(run, warmup, steps)
+        out["tile_B%d_T%d_GBps" % (B, T)] = round(16 * n / ms / 1e6, 1)
+    ms = time_fn(lambda: b.copy_(a), warmup, steps)
+    out["contiguous_copy_GBps"] = round(16 * n / ms / 1e6, 1)
+    return out
+
+
 def workload_mode(args):
     """One secondary workload alone (for rocprofv3): the 64 uneven transforms
     in one persistent graph launch and as per-pass kernels, 512^3 R2C
@@ -231,6 +256,8 @@ def workload_mode(args):
         out.update(nd_4d(torch, time_fn, args.warmup, args.steps))
     elif args.mode == "spectral":
         out.update(spectral_512(torch, np, time_fn, args.warmup, args.steps))
+    elif args.mode == "pattern":
+        out.update(pattern_mode(torch, time_fn, args.warmup, args.steps))
     elif args.mode == "oracle":
         out.update(cpu_baseline_configs(np))
     elif args.mode == "serve":
@@ -352,11 +379,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab", "nd", "spectral", "serve", "oracle"], default="fft",
+    ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab", "nd", "spectral", "serve", "oracle",
+                                       "pattern"], default="fft",
                     help="copy: plain 1 GiB device copy (counter scaling); batched / poisson / "
                          "slab / nd / spectral / serve: only that secondary workload (serve: the "
                          "full 2000-request replay); oracle: the CPU oracle's times for those "
-                         "workloads")
+                         "workloads; pattern: copy rates of the strided passes' access pattern")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -365,7 +393,7 @@ def main():
         sys.exit(2)
     if args.mode == "copy":
         return copy_mode(args)
-    if args.mode in ("batched", "poisson", "slab", "nd", "spectral", "serve", "oracle"):
+    if args.mode in ("batched", "poisson", "slab", "nd", "spectral", "serve", "oracle", "pattern"):
         return workload_mode(args)
 
     import numpy as np

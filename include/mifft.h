@@ -361,6 +361,20 @@ int mifft_profile_end(mifft_plan plan, float* avg_ms, int max_passes, int* npass
 /* Version string of the library build. */
 const char* mifft_version(void);
 
+/* Measurement reference: copies complex elements with the access pattern of
+ * a strided pass and no arithmetic -- for group g < groups, column c < cols
+ * and row r < L, out[g*gs_out + c + r*es_out] = in[g*gs_in + c + r*es_in]
+ * (strides in complex elements), in tiles of B columns x L rows with
+ * threads_per_col threads per column.  Its rate is the ceiling of that access
+ * pattern on the device, against which a strided FFT pass's bandwidth is
+ * read.  The caller owns both buffers and must size them for the largest
+ * offsets; nothing is checked against their extents.  INVALID for NULL or
+ * equal pointers, a non-positive extent, B x threads_per_col > 1024 or a
+ * negative stride. */
+int mifft_pattern_copy(int prec, const void* in, void* out, int L, int cols, int groups, long long es_in,
+                       long long es_out, long long gs_in, long long gs_out, int B, int threads_per_col,
+                       void* stream);
+
 /* One line per compiled kernel variant of a precision -- the autotuner's
  * search space (the candidates MIFFT_TUNE times, in the spirit of the MEASURE
  * planning of Sec. 3): "L=<length> policy=<radix order> emul=<radix groups

@@ -158,6 +158,54 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+// Tile copy with a strided pass's access pattern and no arithmetic: tile
+// (group g, columns c0 .. c0 + B - 1) of L rows; thread (t, c) moves rows t,
+// t + T, ... of column c0 + c, 16 loads in flight before their stores.  The
+// copy rate it reaches is the ceiling of that access pattern on the device
+// (a reference for the strided FFT passes' roofline fraction).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tile_copy(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int L,
+                                                  int cols, int groups, int B, int TT, int tpg, long long es_in,
+                                                  long long es_out, long long gs_in, long long gs_out)
+{
+    const int g = (int)blockIdx.x / tpg;
+    const int col = ((int)blockIdx.x - g * tpg) * B + (int)threadIdx.x % B;
+    const int t = (int)threadIdx.x / B;
+    if (g >= groups || col >= cols) return;
+    const cx<T>* src = in + (long long)g * gs_in + col;
+    cx<T>* dst = out + (long long)g * gs_out + col;
+    constexpr int K = 16;
+    for (int base = t; base < L; base += K * TT) {
+        cx<T> v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int r = base + k * TT;
+            if (r < L) v[k] = src[(long long)r * es_in];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int r = base + k * TT;
+            if (r < L) dst[(long long)r * es_out] = v[k];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_tile_copy(const cx<T>* in, cx<T>* out, int L, int cols, int groups, int B, int TT, long long es_in,
+                            long long es_out, long long gs_in, long long gs_out, hipStream_t s)
+{
+    const int tpg = (cols + B - 1) / B;
+    const long long tiles = (long long)tpg * groups;
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_copy<T>, dim3((unsigned)tiles), dim3(B * TT), 0, s, in, out, L, cols, groups, B, TT, tpg,
+                       es_in, es_out, gs_in, gs_out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_tile_copy<float>(const cx<float>*, cx<float>*, int, int, int, int, int, long long,
+                                            long long, long long, long long, hipStream_t);
+template hipError_t launch_tile_copy<double>(const cx<double>*, cx<double>*, int, int, int, int, int, long long,
+                                             long long, long long, long long, hipStream_t);
 template hipError_t launch_twiddles<float>(cx<float>*, int, hipStream_t);
 template hipError_t launch_twiddles<double>(cx<double>*, int, hipStream_t);
 template hipError_t launch_spectral<float>(const cx<float>*, cx<float>*, int, int, int, int, int, float, float,

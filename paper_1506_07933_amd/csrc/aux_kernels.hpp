@@ -14,5 +14,8 @@ hipError_t launch_pack(const cx<T>* a, cx<T>* s, int n0l, int n1l, int p1, int M
 template <typename T>
 hipError_t launch_unpack(const cx<T>* r, cx<T>* b, int n0l, int n1l, int p1, int M, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+template <typename T>
+hipError_t launch_tile_copy(const cx<T>* in, cx<T>* out, int L, int cols, int groups, int B, int TT, long long es_in,
+                            long long es_out, long long gs_in, long long gs_out, hipStream_t s);
 
 } // namespace mifft

@@ -771,6 +771,25 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
 
 const char* mifft_version(void) { return "mifft 0.1 (gfx950)"; }
 
+int mifft_pattern_copy(int prec, const void* in, void* out, int L, int cols, int groups, long long es_in,
+                       long long es_out, long long gs_in, long long gs_out, int B, int threads_per_col, void* stream)
+{
+    clear_error();
+    if (prec != MIFFT_FP32 && prec != MIFFT_FP64) return set_error(MIFFT_ERR_INVALID, "bad precision %d", prec);
+    if (!in || !out) return set_error(MIFFT_ERR_INVALID, "in / out must not be NULL");
+    if (in == out) return set_error(MIFFT_ERR_INVALID, "in and out must differ");
+    if (L < 1 || cols < 1 || groups < 1 || B < 1 || threads_per_col < 1 || (long long)B * threads_per_col > 1024)
+        return set_error(MIFFT_ERR_INVALID, "bad tile geometry");
+    if (es_in < 0 || es_out < 0 || gs_in < 0 || gs_out < 0) return set_error(MIFFT_ERR_INVALID, "negative stride");
+    hipError_t e = prec == MIFFT_FP64
+                       ? launch_tile_copy<double>((const cx<double>*)in, (cx<double>*)out, L, cols, groups, B,
+                                                  threads_per_col, es_in, es_out, gs_in, gs_out, (hipStream_t)stream)
+                       : launch_tile_copy<float>((const cx<float>*)in, (cx<float>*)out, L, cols, groups, B,
+                                                 threads_per_col, es_in, es_out, gs_in, gs_out, (hipStream_t)stream);
+    if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    return MIFFT_OK;
+}
+
 int mifft_variants_describe(int prec, char* buf, size_t len)
 {
     clear_error();

@@ -353,3 +353,26 @@ def test_pencil_row_group_emulation(prec):
         report("row-group rank %d (%s)" % (j, prec), rel_l2(host(out), ref[:, :, j * pp.m:(j + 1) * pp.m]),
                TOL[prec])
     pp.close()
+
+
+def test_pattern_copy_reference_kernel():
+    """The access-pattern reference copy moves exactly the elements its
+    strides name (ragged tiles included)."""
+    from paper_1506_07933_amd._lib import lib
+    L, cols, groups = 40, 45, 3
+    es_in, gs_in = 48, 48 * 40          # rows of 48 (45 used), groups of 40 rows
+    es_out, gs_out = 3 * 45, 45         # written transposed: [row][group][col]
+    src = synth.uniform_complex((groups * gs_in,), np.complex64, seed=11)
+    a = gpu(src)
+    b = torch.zeros(L * es_out, dtype=torch.complex64, device=DEV)
+    assert lib.mifft_pattern_copy(0, a.data_ptr(), b.data_ptr(), L, cols, groups, es_in, es_out, gs_in, gs_out,
+                                  16, 8, None) == 0
+    got = host(b)
+    want = np.zeros(L * es_out, dtype=np.complex64)
+    for g in range(groups):
+        for r in range(L):
+            want[g * gs_out + r * es_out: g * gs_out + r * es_out + cols] = \
+                src[g * gs_in + r * es_in: g * gs_in + r * es_in + cols]
+    np.testing.assert_array_equal(got, want)
+    assert lib.mifft_pattern_copy(0, a.data_ptr(), a.data_ptr(), L, cols, groups, es_in, es_out, gs_in, gs_out,
+                                  16, 8, None) == 1
