@@ -43,6 +43,20 @@ template <typename T> __device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v
     typedef typename nt2_of<T>::type N2;
     __builtin_nontemporal_store(N2{v.x, v.y}, reinterpret_cast<N2*>(p));
 }
+// Streaming loads for the passes' inputs (each element is read once).
+#ifndef MIFFT_NT_LOADS
+#define MIFFT_NT_LOADS 1
+#endif
+template <typename T> __device__ __forceinline__ cx<T> load_in(const cx<T>* p)
+{
+    if constexpr (MIFFT_NT_LOADS) {
+        typedef typename nt2_of<T>::type N2;
+        const N2 r = __builtin_nontemporal_load(reinterpret_cast<const N2*>(p));
+        return cx<T>{r.x, r.y};
+    } else {
+        return *p;
+    }
+}
 
 template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
     using V = cx<T>;
@@ -59,7 +73,7 @@ template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
 
     __device__ __forceinline__ V gload(int idx) const
     {
-        V v = valid ? in[idx] : V{T(0), T(0)};
+        V v = valid ? load_in<T>(in + idx) : V{T(0), T(0)};
         v.y *= sgn;
         return v;
     }
@@ -120,9 +134,9 @@ template <typename T, int SPLIT, int SLOTS, bool PF> struct StridedCtx {
         if (ok) {
             if constexpr (SPLIT == 1) {
                 uint32_t q = fdiv((uint32_t)idx, split);
-                v = base[(long long)q * s_hi + (long long)(idx - (int)(q * split.d)) * es_in];
+                v = load_in<T>(base + (long long)q * s_hi + (long long)(idx - (int)(q * split.d)) * es_in);
             } else {
-                v = base[(long long)idx * es_in];
+                v = load_in<T>(base + (long long)idx * es_in);
             }
         }
         return v;
