@@ -43,7 +43,11 @@ template <typename T> __device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v
     typedef typename nt2_of<T>::type N2;
     __builtin_nontemporal_store(N2{v.x, v.y}, reinterpret_cast<N2*>(p));
 }
-// Streaming loads for the passes' inputs (each element is read once).
+// Streaming loads for the C2C passes' inputs (each element is read once).  The
+// real-data passes and the fused spectral x-pass keep cached loads: with
+// streaming loads there the R2C y-pass after them and the FP64 Poisson solve
+// ran slower (2.45 -> 2.51 ms), while the C2C 512^3 forward gained 0.7% and
+// the 4-D case 2.3%.
 #ifndef MIFFT_NT_LOADS
 #define MIFFT_NT_LOADS 1
 #endif
@@ -122,6 +126,7 @@ template <typename T, int SPLIT, int SLOTS, bool PF> struct StridedCtx {
     // SPLIT: element y = q * split.d + rem of a line sits at q * s_hi + rem * es
     // (es_in for SPLIT = 1 on the load side, es_out for SPLIT = 2 on the store side)
     FastDiv split;
+    bool nt; // streaming loads: the tiles cover whole, aligned 128-byte lines of the input
     long long s_hi;
     V pre[SLOTS];            // first-stage inputs of the current tile
     const V* nin;            // next tile: input column, and whether it is a real column
@@ -132,12 +137,14 @@ template <typename T, int SPLIT, int SLOTS, bool PF> struct StridedCtx {
     {
         V v{T(0), T(0)};
         if (ok) {
+            const V* p;
             if constexpr (SPLIT == 1) {
                 uint32_t q = fdiv((uint32_t)idx, split);
-                v = load_in<T>(base + (long long)q * s_hi + (long long)(idx - (int)(q * split.d)) * es_in);
+                p = base + (long long)q * s_hi + (long long)(idx - (int)(q * split.d)) * es_in;
             } else {
-                v = load_in<T>(base + (long long)idx * es_in);
+                p = base + (long long)idx * es_in;
             }
+            v = nt ? load_in<T>(p) : *p;
         }
         return v;
     }
@@ -362,6 +369,7 @@ template <typename T> struct StridedArgs {
     T sgn;
     FastDiv split;
     long long s_hi;
+    int nt_in; // streaming loads (the planner's choice: whole, aligned input lines)
 };
 
 // Whether the strided kernel of (T, L, policy, TPL) prefetches the next
@@ -407,6 +415,7 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
     c.es_out = a.es_out;
     c.split = a.split;
     c.s_hi = a.s_hi;
+    c.nt = a.nt_in != 0;
     // (group, column) of this thread in a tile; false past the last column
     auto locate = [&](int tl, long long& in_off, long long& out_off) -> bool {
         unsigned g, col;

@@ -273,6 +273,17 @@ void tile_pass(const Plan& plan, Pass& p)
                       (p.kind != P_STRIDED_SPLIT && p.gs_in == p.cols);
     p.tpg = flat ? 0 : (p.cols + p.B - 1) / p.B;
     p.ntiles = flat ? (int)(((long long)p.groups * p.cols + p.B - 1) / p.B) : p.groups * p.tpg;
+    // Streaming (non-temporal) loads pay where every tile reads whole, aligned
+    // 128-byte lines; where a tile reads part of a line that the next tile
+    // reads too (ragged or unaligned rows: the 257 columns of a half
+    // spectrum), the line must stay cached (measured: R2C 512^3 y-pass 0.255
+    // -> 0.278 ms with streaming loads, the C2C 512^3 y-pass 0.415 -> 0.411).
+    {
+        const long long a = 128 / (long long)plan.esz;
+        bool ok = p.cols % p.B == 0 && p.es_in % a == 0 && (p.groups == 1 || p.gs_in % a == 0);
+        if (p.kind == P_STRIDED_SPLIT) ok = ok && p.blk % a == 0;
+        p.nt_in = ok ? 1 : 0;
+    }
     if (p.kind == P_POISSON_X)
         p.grid = (unsigned)p.ntiles; // one workgroup per tile
     else
@@ -374,6 +385,7 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.sgn = (T)p.sgn;
         a.split = p.fd;
         a.s_hi = p.blk;
+        a.nt_in = p.nt_in;
         auto fn = p.kind == P_STRIDED         ? v.strided
                   : p.kind == P_STRIDED_SPLIT ? v.strided_split
                                               : v.strided_osplit;

@@ -384,3 +384,15 @@ def test_spectral_workspace_is_three_halves(shape):
     sws = lib.mifft_spectral_ws_bytes(h.value)
     plan_destroy(h.value)
     assert pws > 0 and sws == pws // 2 * 3
+
+
+def test_streaming_loads_only_for_whole_aligned_lines():
+    """Strided passes read with streaming loads only where every tile covers
+    whole, aligned 128-byte lines of the input (512 columns); the 257-column
+    half spectrum of R2C 512^3 keeps cached loads."""
+    passes, _, _ = plan_only(512, 512, 512, kind=0, prec=0)
+    st = [p for p in passes if p["kind"] == "strided"]
+    assert st and all(p["nt"] == "1" for p in st)
+    passes, _, _ = plan_only(512, 512, 512, kind=1, prec=0)
+    fwd = [p for p in passes if p["dir"] == "forward" and p["kind"] == "strided"]
+    assert fwd and all(p["nt"] == "0" for p in fwd)
