@@ -214,8 +214,8 @@ def pattern_mode(torch, time_fn, warmup, steps):
     out = {}
     for B, T in ((32, 32), (32, 16), (64, 16), (16, 64), (128, 8)):
         def run():
-            check(lib.mifft_pattern_copy(0, a.data_ptr(), b.data_ptr(), 512, 512, 512, 512, 512 * 512,
-                                         512 * 512, 512, B, T, torch.cuda.current_stream().cuda_stream),
+            check(lib.mifft_pattern_copy(0, a.data_ptr(), n, b.data_ptr(), n, 512, 512, 512, 512, 512 * 512,
+                                         512 * 512, 512, B, T, 3, torch.cuda.current_stream().cuda_stream),
                   "mifft_pattern_copy")
         ms = time_fn(run, warmup, steps)
         out["tile_B%d_T%d_GBps" % (B, T)] = round(16 * n / ms / 1e6, 1)

@@ -88,7 +88,11 @@ typedef enum {
                                   per transform) */
 #define MIFFT_PLAN_ONLY 2u /* build the pass list without touching the device: the
                               plan can be described (mifft_plan_describe) and
-                              destroyed, execute calls return MIFFT_ERR_BADPLAN */
+                              destroyed, execute calls return MIFFT_ERR_BADPLAN.
+                              With MIFFT_TUNE, the choices stored in the wisdom
+                              file are applied and nothing is timed; entries with
+                              a tile width that is not a power of two in 1 .. 64,
+                              or lines per workgroup outside 1 .. 32, are ignored */
 
 /* Longest axis a single-pass kernel handles. */
 #define MIFFT_MAX_AXIS 1024
@@ -361,19 +365,35 @@ int mifft_profile_end(mifft_plan plan, float* avg_ms, int max_passes, int* npass
 /* Version string of the library build. */
 const char* mifft_version(void);
 
-/* Measurement reference: copies complex elements with the access pattern of
- * a strided pass and no arithmetic -- for group g < groups, column c < cols
+/* Measurement references (flags: MIFFT_COPY_NT_LOADS / MIFFT_COPY_NT_STORES
+ * select streaming loads / stores, as the FFT passes use them).
+ *
+ * mifft_pattern_copy copies complex elements with the access pattern of a
+ * strided pass and no arithmetic -- for group g < groups, column c < cols
  * and row r < L, out[g*gs_out + c + r*es_out] = in[g*gs_in + c + r*es_in]
  * (strides in complex elements), in tiles of B columns x L rows with
  * threads_per_col threads per column.  Its rate is the ceiling of that access
  * pattern on the device, against which a strided FFT pass's bandwidth is
- * read.  The caller owns both buffers and must size them for the largest
- * offsets; nothing is checked against their extents.  INVALID for NULL or
- * equal pointers, a non-positive extent, B x threads_per_col > 1024 or a
- * negative stride. */
-int mifft_pattern_copy(int prec, const void* in, void* out, int L, int cols, int groups, long long es_in,
-                       long long es_out, long long gs_in, long long gs_out, int B, int threads_per_col,
-                       void* stream);
+ * read.  The caller owns both buffers; in_elems / out_elems are their sizes
+ * in complex elements.  INVALID, before anything is launched, for NULL
+ * pointers, pointers not aligned to the element, a non-positive extent,
+ * B x threads_per_col > 1024, a negative stride, unknown flags, offsets
+ * reaching past in_elems / out_elems, or overlapping source and destination
+ * ranges. */
+#define MIFFT_COPY_NT_LOADS 1u
+#define MIFFT_COPY_NT_STORES 2u
+int mifft_pattern_copy(int prec, const void* in, size_t in_elems, void* out, size_t out_elems, int L, int cols,
+                       int groups, long long es_in, long long es_out, long long gs_in, long long gs_out, int B,
+                       int threads_per_col, unsigned flags, void* stream);
+
+/* mifft_copy_reference copies `bytes` (a multiple of 16) from in to out with
+ * 16-byte vector accesses, several in flight per thread, over `grid`
+ * workgroups of 256 threads (0: enough for four words per thread) -- the
+ * plain contiguous copy, the achievable bandwidth ceiling of the device.
+ * Both buffers hold at least `bytes` and are caller-owned.  INVALID for NULL
+ * or unaligned pointers, a size not a multiple of 16, a negative grid,
+ * unknown flags or overlapping ranges. */
+int mifft_copy_reference(const void* in, void* out, size_t bytes, unsigned flags, int grid, void* stream);
 
 /* One line per compiled kernel variant of a precision -- the autotuner's
  * search space (the candidates MIFFT_TUNE times, in the spirit of the MEASURE

@@ -70,7 +70,6 @@ def _load():
             dp = ctypes.POINTER(ctypes.c_double)
             i64 = ctypes.c_int64
             ci = ctypes.c_int
-            lib.oracle_fft1d.argtypes = [dp, i64, ci, ci]
             lib.oracle_fft3d_c2c.argtypes = [dp, ci, ci, ci, ci]
             lib.oracle_fft_axis.argtypes = [dp, i64, ci, i64, ci]
             lib.oracle_fft3d_r2c.argtypes = [dp, dp, ci, ci, ci]
@@ -79,7 +78,7 @@ def _load():
             lib.oracle_poisson_half.argtypes = [dp, ci, ci, ci, ctypes.c_double]
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ci
-            for f in (lib.oracle_fft1d, lib.oracle_fft3d_c2c, lib.oracle_fft_axis,
+            for f in (lib.oracle_fft3d_c2c, lib.oracle_fft_axis,
                       lib.oracle_fft3d_r2c, lib.oracle_fft3d_c2r, lib.oracle_c2r_z,
                       lib.oracle_poisson_half):
                 f.restype = None
@@ -98,15 +97,6 @@ def _dptr(a: np.ndarray):
 
 def _as_c128(x) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(x), dtype=np.complex128).copy()
-
-
-def fft1d(x, sign: int = -1) -> np.ndarray:
-    """Unscaled 1-D DFT of every row of a 2-D (batch, n) array."""
-    a = _as_c128(x)
-    if a.ndim == 1:
-        a = a[None, :]
-    _load().oracle_fft1d(_dptr(a), a.shape[0], a.shape[1], int(sign))
-    return a
 
 
 def fft3d_c2c(x, sign: int = -1) -> np.ndarray:

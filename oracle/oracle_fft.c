@@ -219,12 +219,6 @@ int oracle_max_threads(void)
 #endif
 }
 
-/* 1-D transform of `batch` contiguous lines of length n, in place. */
-void oracle_fft1d(double* data, int64_t batch, int n, int sign)
-{
-    fft_axis((cplx*)data, batch, n, 1, sign);
-}
-
 /* 3-D C2C in place on interleaved complex doubles; Algorithm 1 order z,y,x. */
 void oracle_fft3d_c2c(double* data, int n0, int n1, int n2, int sign)
 {

@@ -57,8 +57,9 @@ SIGNATURES = {
                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "mifft_version": (ctypes.c_char_p, []),
     "mifft_variants_describe": (_i, [_i, ctypes.c_char_p, _sz]),
-    "mifft_pattern_copy": (_i, [_i, _cvp, _vp, _i, _i, _i, ctypes.c_longlong, ctypes.c_longlong,
-                                ctypes.c_longlong, ctypes.c_longlong, _i, _i, _vp]),
+    "mifft_pattern_copy": (_i, [_i, _cvp, _sz, _vp, _sz, _i, _i, _i, ctypes.c_longlong, ctypes.c_longlong,
+                                ctypes.c_longlong, ctypes.c_longlong, _i, _i, ctypes.c_uint, _vp]),
+    "mifft_copy_reference": (_i, [_cvp, _vp, _sz, ctypes.c_uint, _i, _vp]),
 }
 
 

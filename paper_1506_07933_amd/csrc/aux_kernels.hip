@@ -162,12 +162,14 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
 // (group g, columns c0 .. c0 + B - 1) of L rows; thread (t, c) moves rows t,
 // t + T, ... of column c0 + c, 16 loads in flight before their stores.  The
 // copy rate it reaches is the ceiling of that access pattern on the device
-// (a reference for the strided FFT passes' roofline fraction).
-template <typename T>
+// (a reference for the strided FFT passes' roofline fraction).  NTL / NTS:
+// streaming (non-temporal) loads / stores, as the FFT passes use them.
+template <typename T, bool NTL, bool NTS>
 __global__ __launch_bounds__(1024) void k_tile_copy(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int L,
                                                   int cols, int groups, int B, int TT, int tpg, long long es_in,
                                                   long long es_out, long long gs_in, long long gs_out)
 {
+    typedef typename nt_vec2<T>::type N2;
     const int g = (int)blockIdx.x / tpg;
     const int col = ((int)blockIdx.x - g * tpg) * B + (int)threadIdx.x % B;
     const int t = (int)threadIdx.x / B;
@@ -176,36 +178,103 @@ __global__ __launch_bounds__(1024) void k_tile_copy(const cx<T>* __restrict__ in
     cx<T>* dst = out + (long long)g * gs_out + col;
     constexpr int K = 16;
     for (int base = t; base < L; base += K * TT) {
-        cx<T> v[K];
+        N2 v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int r = base + k * TT;
-            if (r < L) v[k] = src[(long long)r * es_in];
+            if (r < L) {
+                const N2* q = reinterpret_cast<const N2*>(src + (long long)r * es_in);
+                if constexpr (NTL)
+                    v[k] = __builtin_nontemporal_load(q);
+                else
+                    v[k] = *q;
+            }
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int r = base + k * TT;
-            if (r < L) dst[(long long)r * es_out] = v[k];
+            if (r < L) {
+                N2* q = reinterpret_cast<N2*>(dst + (long long)r * es_out);
+                if constexpr (NTS)
+                    __builtin_nontemporal_store(v[k], q);
+                else
+                    *q = v[k];
+            }
         }
     }
 }
 
 template <typename T>
 hipError_t launch_tile_copy(const cx<T>* in, cx<T>* out, int L, int cols, int groups, int B, int TT, long long es_in,
-                            long long es_out, long long gs_in, long long gs_out, hipStream_t s)
+                            long long es_out, long long gs_in, long long gs_out, unsigned flags, hipStream_t s)
 {
     const int tpg = (cols + B - 1) / B;
     const long long tiles = (long long)tpg * groups;
     if (tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_copy<T>, dim3((unsigned)tiles), dim3(B * TT), 0, s, in, out, L, cols, groups, B, TT, tpg,
-                       es_in, es_out, gs_in, gs_out);
+    auto fn = (flags & 3u) == 3u ? k_tile_copy<T, true, true>
+              : (flags & 1u)     ? k_tile_copy<T, true, false>
+              : (flags & 2u)     ? k_tile_copy<T, false, true>
+                                 : k_tile_copy<T, false, false>;
+    hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(B * TT), 0, s, in, out, L, cols, groups, B, TT, tpg, es_in,
+                       es_out, gs_in, gs_out);
+    return hipGetLastError();
+}
+
+// Contiguous reference copy of n16 16-byte words: each thread moves U words
+// per grid-stride round (all loads issued before the stores), with optional
+// streaming loads / stores -- the best plain copy this device reaches, the
+// achievable ceiling the passes' bandwidth is read against.
+template <bool NTL, bool NTS>
+__global__ __launch_bounds__(256) void k_copy_ref(const uint4* __restrict__ a, uint4* __restrict__ b, long long n16)
+{
+    typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+    constexpr int U = 4;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x; i0 < n16; i0 += U * stride) {
+        U4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long i = i0 + u * stride;
+            if (i < n16) {
+                const U4* q = reinterpret_cast<const U4*>(a + i);
+                if constexpr (NTL)
+                    v[u] = __builtin_nontemporal_load(q);
+                else
+                    v[u] = *q;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long i = i0 + u * stride;
+            if (i < n16) {
+                U4* q = reinterpret_cast<U4*>(b + i);
+                if constexpr (NTS)
+                    __builtin_nontemporal_store(v[u], q);
+                else
+                    *q = v[u];
+            }
+        }
+    }
+}
+
+hipError_t launch_copy_ref(const void* src, void* dst, size_t bytes, unsigned flags, int grid, hipStream_t s)
+{
+    const long long n16 = (long long)(bytes / 16);
+    if (n16 == 0) return hipSuccess;
+    long long blocks = grid > 0 ? grid : (n16 + 4 * 256 - 1) / (4 * 256);
+    if (blocks > (1LL << 30)) blocks = 1LL << 30;
+    auto fn = (flags & 3u) == 3u ? k_copy_ref<true, true>
+              : (flags & 1u)     ? k_copy_ref<true, false>
+              : (flags & 2u)     ? k_copy_ref<false, true>
+                                 : k_copy_ref<false, false>;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
     return hipGetLastError();
 }
 
 template hipError_t launch_tile_copy<float>(const cx<float>*, cx<float>*, int, int, int, int, int, long long,
-                                            long long, long long, long long, hipStream_t);
+                                            long long, long long, long long, unsigned, hipStream_t);
 template hipError_t launch_tile_copy<double>(const cx<double>*, cx<double>*, int, int, int, int, int, long long,
-                                             long long, long long, long long, hipStream_t);
+                                             long long, long long, long long, unsigned, hipStream_t);
 template hipError_t launch_twiddles<float>(cx<float>*, int, hipStream_t);
 template hipError_t launch_twiddles<double>(cx<double>*, int, hipStream_t);
 template hipError_t launch_spectral<float>(const cx<float>*, cx<float>*, int, int, int, int, int, float, float,

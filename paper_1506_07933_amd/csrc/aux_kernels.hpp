@@ -16,6 +16,12 @@ hipError_t launch_unpack(const cx<T>* r, cx<T>* b, int n0l, int n1l, int p1, int
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 template <typename T>
 hipError_t launch_tile_copy(const cx<T>* in, cx<T>* out, int L, int cols, int groups, int B, int TT, long long es_in,
-                            long long es_out, long long gs_in, long long gs_out, hipStream_t s);
+                            long long es_out, long long gs_in, long long gs_out, unsigned flags, hipStream_t s);
+hipError_t launch_copy_ref(const void* src, void* dst, size_t bytes, unsigned flags, int grid, hipStream_t s);
+
+// 2-vectors of T for the streaming-load / -store builtins
+template <typename T> struct nt_vec2;
+template <> struct nt_vec2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct nt_vec2<double> { typedef double type __attribute__((ext_vector_type(2))); };
 
 } // namespace mifft

@@ -111,6 +111,10 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
     if ((flags & MIFFT_BATCH_GROUPED) && (flags & MIFFT_BATCH_KERNELS))
         return set_error(MIFFT_ERR_INVALID, "MIFFT_BATCH_GROUPED and MIFFT_BATCH_KERNELS exclude each other");
     if (kind != MIFFT_C2C) return set_error(MIFFT_ERR_UNSUPPORTED, "batches are C2C only");
+    if ((flags & MIFFT_TUNE) && !(flags & (MIFFT_BATCH_KERNELS | MIFFT_BATCH_GROUPED)))
+        return set_error(MIFFT_ERR_UNSUPPORTED,
+                         "MIFFT_TUNE tunes the per-pass plans of MIFFT_BATCH_KERNELS / MIFFT_BATCH_GROUPED; "
+                         "the persistent kernel has one compiled code path per length");
     if (count > kBatchMax) return set_error(MIFFT_ERR_UNSUPPORTED, "at most %d transforms per batch", kBatchMax);
     const bool grouped = flags & MIFFT_BATCH_GROUPED;
     const bool kernels = (flags & MIFFT_BATCH_KERNELS) || grouped;

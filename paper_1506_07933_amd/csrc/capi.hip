@@ -113,8 +113,6 @@ int mifft_plan_create(mifft_plan* out, int n0, int n1, int n2, int kind, int pre
     if (flags & ~(unsigned)(MIFFT_TUNE | MIFFT_PLAN_ONLY))
         return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
     const bool plan_only = flags & MIFFT_PLAN_ONLY;
-    if (plan_only && (flags & MIFFT_TUNE))
-        return set_error(MIFFT_ERR_INVALID, "MIFFT_TUNE needs the device; it cannot be combined with MIFFT_PLAN_ONLY");
     int dev = 0;
     if (!plan_only && (rc = check_device(&dev))) return rc;
     mifft_plan_s* p = new mifft_plan_s();
@@ -771,21 +769,55 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
 
 const char* mifft_version(void) { return "mifft 0.1 (gfx950)"; }
 
-int mifft_pattern_copy(int prec, const void* in, void* out, int L, int cols, int groups, long long es_in,
-                       long long es_out, long long gs_in, long long gs_out, int B, int threads_per_col, void* stream)
+int mifft_pattern_copy(int prec, const void* in, size_t in_elems, void* out, size_t out_elems, int L, int cols,
+                       int groups, long long es_in, long long es_out, long long gs_in, long long gs_out, int B,
+                       int threads_per_col, unsigned flags, void* stream)
 {
     clear_error();
     if (prec != MIFFT_FP32 && prec != MIFFT_FP64) return set_error(MIFFT_ERR_INVALID, "bad precision %d", prec);
     if (!in || !out) return set_error(MIFFT_ERR_INVALID, "in / out must not be NULL");
-    if (in == out) return set_error(MIFFT_ERR_INVALID, "in and out must differ");
+    if (flags & ~(unsigned)(MIFFT_COPY_NT_LOADS | MIFFT_COPY_NT_STORES))
+        return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    const size_t esz = prec == MIFFT_FP64 ? 16 : 8;
+    if ((uintptr_t)in % esz || (uintptr_t)out % esz)
+        return set_error(MIFFT_ERR_INVALID, "in / out must be aligned to the complex element");
     if (L < 1 || cols < 1 || groups < 1 || B < 1 || threads_per_col < 1 || (long long)B * threads_per_col > 1024)
         return set_error(MIFFT_ERR_INVALID, "bad tile geometry");
     if (es_in < 0 || es_out < 0 || gs_in < 0 || gs_out < 0) return set_error(MIFFT_ERR_INVALID, "negative stride");
+    // one past the largest element offset read / written, in exact integer arithmetic
+    const unsigned __int128 ein = (unsigned __int128)(groups - 1) * (unsigned long long)gs_in + (unsigned)(cols - 1) +
+                                  (unsigned __int128)(L - 1) * (unsigned long long)es_in + 1;
+    const unsigned __int128 eout = (unsigned __int128)(groups - 1) * (unsigned long long)gs_out +
+                                   (unsigned)(cols - 1) + (unsigned __int128)(L - 1) * (unsigned long long)es_out + 1;
+    if (ein > in_elems || eout > out_elems)
+        return set_error(MIFFT_ERR_INVALID, "pattern reaches %llu / %llu elements of buffers holding %zu / %zu",
+                         (unsigned long long)ein, (unsigned long long)eout, in_elems, out_elems);
+    const uintptr_t a0 = (uintptr_t)in, a1 = a0 + (uintptr_t)(ein * esz);
+    const uintptr_t b0 = (uintptr_t)out, b1 = b0 + (uintptr_t)(eout * esz);
+    if (a0 < b1 && b0 < a1) return set_error(MIFFT_ERR_INVALID, "in and out overlap");
     hipError_t e = prec == MIFFT_FP64
                        ? launch_tile_copy<double>((const cx<double>*)in, (cx<double>*)out, L, cols, groups, B,
-                                                  threads_per_col, es_in, es_out, gs_in, gs_out, (hipStream_t)stream)
+                                                  threads_per_col, es_in, es_out, gs_in, gs_out, flags,
+                                                  (hipStream_t)stream)
                        : launch_tile_copy<float>((const cx<float>*)in, (cx<float>*)out, L, cols, groups, B,
-                                                 threads_per_col, es_in, es_out, gs_in, gs_out, (hipStream_t)stream);
+                                                 threads_per_col, es_in, es_out, gs_in, gs_out, flags,
+                                                 (hipStream_t)stream);
+    if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    return MIFFT_OK;
+}
+
+int mifft_copy_reference(const void* in, void* out, size_t bytes, unsigned flags, int grid, void* stream)
+{
+    clear_error();
+    if (!in || !out) return set_error(MIFFT_ERR_INVALID, "in / out must not be NULL");
+    if (flags & ~(unsigned)(MIFFT_COPY_NT_LOADS | MIFFT_COPY_NT_STORES))
+        return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if ((uintptr_t)in % 16 || (uintptr_t)out % 16 || bytes % 16)
+        return set_error(MIFFT_ERR_INVALID, "pointers and size must be multiples of 16 bytes");
+    if (grid < 0) return set_error(MIFFT_ERR_INVALID, "negative grid");
+    const uintptr_t a0 = (uintptr_t)in, b0 = (uintptr_t)out;
+    if (bytes && a0 < b0 + bytes && b0 < a0 + bytes) return set_error(MIFFT_ERR_INVALID, "in and out overlap");
+    hipError_t e = launch_copy_ref(in, out, bytes, flags, grid, (hipStream_t)stream);
     if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
     return MIFFT_OK;
 }

@@ -36,6 +36,18 @@ static bool g_wisdom_loaded = false;
 
 static const char* wisdom_path() { return getenv("MIFFT_WISDOM"); }
 
+// A strided kernel maps thread tid to column tid & (B - 1) and line thread
+// tid >> log2(B), which covers each column once only for B a power of two;
+// tiles are at most 64 columns wide and 1024 threads.  A contiguous pass
+// takes 1 .. 32 lines per workgroup.  Entries of a wisdom file (which may
+// have been edited by hand) outside these ranges are ignored.
+static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+static bool choice_shape_ok(const Choice& c)
+{
+    if (c.policy < 0 || c.policy > 2 || c.emul < 1 || c.emul > 2) return false;
+    return (c.B == 0 && c.lpw >= 1 && c.lpw <= 32) || (c.lpw == 0 && pow2_in(c.B, 1, 64));
+}
+
 // One entry per line:  "key": [policy, emul, B, lpw, microseconds],
 static void load_wisdom_locked()
 {
@@ -49,7 +61,8 @@ static void load_wisdom_locked()
         const size_t a = line.find('"'), b = line.find('"', a + 1), c = line.find('[', b);
         if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
         Choice ch;
-        if (sscanf(line.c_str() + c, "[%d, %d, %d, %d, %lf]", &ch.policy, &ch.emul, &ch.B, &ch.lpw, &ch.us) == 5)
+        if (sscanf(line.c_str() + c, "[%d, %d, %d, %d, %lf]", &ch.policy, &ch.emul, &ch.B, &ch.lpw, &ch.us) == 5 &&
+            choice_shape_ok(ch))
             g_wisdom[line.substr(a + 1, b - a - 1)] = ch;
     }
 }
@@ -105,7 +118,8 @@ static bool apply_choice(const Plan& plan, Pass& p, int vidx, int shape)
     const size_t esz = plan.esz;
     if (p.kind == P_STRIDED) {
         const int B = shape;
-        if ((long long)B * tpl > 1024 || (size_t)(B + 1) * p.L * esz > 160 * 1024) return false;
+        if (!pow2_in(B, 1, 64) || (long long)B * tpl > 1024 || (size_t)(B + 1) * p.L * esz > 160 * 1024)
+            return false;
         int lg = 0;
         while ((1 << lg) < B) ++lg;
         p.vidx = vidx;
@@ -117,7 +131,8 @@ static bool apply_choice(const Plan& plan, Pass& p, int vidx, int shape)
         return true;
     }
     const int lpw = shape;
-    if ((long long)lpw * tpl > 1024 || ((size_t)lpw * lds_len_of(p) + p.L) * esz > 160 * 1024) return false;
+    if (lpw < 1 || lpw > 32 || (long long)lpw * tpl > 1024 || ((size_t)lpw * lds_len_of(p) + p.L) * esz > 160 * 1024)
+        return false;
     const int ni = p.ni;
     const long long is_o = p.is_o, is_i = p.is_i, os_o = p.os_o, os_i = p.os_i;
     p.vidx = vidx;
@@ -147,12 +162,44 @@ static std::vector<std::pair<int, int>> candidates(const Plan& plan, const Pass&
     return out;
 }
 
+// Re-shape every tunable pass that has a wisdom entry; returns whether all had one.
+static bool apply_wisdom_locked(Plan& plan, const char* arch)
+{
+    bool all = true;
+    for (auto* list : {&plan.fwd, &plan.inv})
+        for (Pass& p : *list) {
+            if (!is_tunable(p)) continue;
+            auto it = g_wisdom.find(pass_key(plan, p, arch));
+            bool done = false;
+            if (it != g_wisdom.end()) {
+                const int v = find_variant(plan.prec, p.L, it->second.policy, it->second.emul);
+                Pass q = p;
+                if (v >= 0 && apply_choice(plan, q, v, p.kind == P_STRIDED ? it->second.B : it->second.lpw)) {
+                    p = q;
+                    done = true;
+                }
+            }
+            all = all && done;
+        }
+    return all;
+}
+
 int tune_plan(Plan& plan)
 {
+    char arch[64];
+    if (plan.plan_only) {
+        // no device: apply the stored choices for the one target this library is built for
+        snprintf(arch, sizeof(arch), "gfx950");
+        std::lock_guard<std::mutex> g(g_wmu);
+        load_wisdom_locked();
+        apply_wisdom_locked(plan, arch);
+        rebuild_poisson(plan);
+        tile_passes(plan);
+        return validate_extents(plan);
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, plan.device) != hipSuccess)
         return set_error(MIFFT_ERR_DEVICE, "tuning: device properties");
-    char arch[64];
     snprintf(arch, sizeof(arch), "%.*s", 6, prop.gcnArchName);
     std::lock_guard<std::mutex> g(g_wmu);
     load_wisdom_locked();

@@ -7,21 +7,26 @@ clock).  Each request is one periodic Poisson solve lap(u) = f on an n^3 grid
 
 Scheduling (SchedulerCore, pure host logic):
   * arrived requests wait in a FIFO queue;
-  * the head of the queue is admitted as soon as a slot is free and its
-    device bytes (output + workspace) fit in the HBM budget on top of the
-    bytes of the requests in flight; a request that could never fit is
-    rejected at once with an error record instead of blocking the queue;
+  * the HBM budget is one device pool of exactly that many bytes, allocated
+    once; the head of the queue is admitted as soon as a slot is free and
+    its device bytes (right-hand side + output + workspace) can be carved
+    out of the pool (PoolAllocator: first fit, 256-byte aligned, freed
+    ranges coalesce), so the budget bounds the memory requests really hold;
+    a request larger than the whole pool is rejected at once with an error
+    record instead of blocking the queue;
   * admitted requests are enqueued on their slot's stream, so work of
     different requests overlaps on the device; completions are polled and
-    free their slot and bytes immediately, which is what lets requests that
-    arrive while others run join the device work (continuous batching);
+    return their slot and pool range immediately, which is what lets
+    requests that arrive while others run join the device work (continuous
+    batching);
   * an executor failure fails only that request.
 Latency = completion time - scheduled arrival time.
 
 GpuPoissonExecutor keeps one plan per (n, precision) resident (twiddles on the
-device), one stream per slot, a device-resident pool of right-hand sides, and
-one preallocated arena per slot that holds the largest request's output and
-workspace, so serving allocates nothing; every (n, precision) is run once at
+device), one stream per slot and the pool.  Each request draws its own
+right-hand side on its slot's stream into its pool range (the Poisson recipe:
+8 random Fourier modes plus N(0, 0.01) noise, seeded per request), then
+solves; serving allocates nothing.  Every (n, precision) is run once at
 start-up so no request pays for loading kernels.
 """
 from __future__ import annotations
@@ -62,21 +67,73 @@ class Record:
         return self.t_done - self.t_arrival
 
 
+class PoolAllocator:
+    """First-fit sub-allocation of one buffer of `size` bytes (offsets only;
+    the executor owns the memory).  Ranges are rounded up to `align` bytes;
+    a freed range is merged with free neighbours, so the pool never holds
+    two adjacent free ranges."""
+
+    def __init__(self, size: int, align: int = 256):
+        if size < 1 or align < 1:
+            raise ValueError("pool size and alignment must be positive")
+        self.size = int(size) // align * align
+        self.align = int(align)
+        self.free: List[List[int]] = [[0, self.size]] if self.size else []
+        self.used = 0
+
+    def _round(self, nbytes: int) -> int:
+        return max(1, -(-int(nbytes) // self.align)) * self.align
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        n = self._round(nbytes)
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = [off + n, ln - n]
+                self.used += n
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int) -> None:
+        n = self._round(nbytes)
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        if (i > 0 and self.free[i - 1][0] + self.free[i - 1][1] > off) or \
+                (i < len(self.free) and off + n > self.free[i][0]) or off < 0 or off + n > self.size:
+            raise ValueError("release of [%d, %d) overlaps free memory" % (off, off + n))
+        self.free.insert(i, [off, n])
+        if i + 1 < len(self.free) and off + n == self.free[i + 1][0]:
+            self.free[i][1] += self.free[i + 1][1]
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            self.free[i - 1][1] += self.free[i][1]
+            del self.free[i]
+        self.used -= n
+
+    def fits(self, nbytes: int) -> bool:
+        return self._round(nbytes) <= self.size
+
+
 class SchedulerCore:
-    """FIFO admission by slots and HBM budget; executor-agnostic.
+    """FIFO admission by slots and a pool of `budget_bytes`; executor-agnostic.
 
     executor must provide:
       bytes_needed(req) -> int
-      submit(req, slot) -> handle       (enqueue device work; may raise)
-      poll(handle) -> bool              (True once the work has completed; may raise)
-      release(handle)                   (free the request's buffers)
+      submit(req, slot, offset) -> handle  (enqueue device work using the pool
+                                           range at `offset`; may raise)
+      poll(handle) -> bool                 (True once the work has completed; may raise)
+      release(handle)                      (called before the range returns to the pool)
     """
 
     def __init__(self, executor, budget_bytes: int, slots: int):
         if slots < 1 or budget_bytes < 1:
             raise ValueError("need at least one slot and a positive budget")
         self.ex = executor
-        self.budget = int(budget_bytes)
+        self.pool = PoolAllocator(int(budget_bytes))
+        self.budget = self.pool.size
         self.free_slots = list(range(slots))[::-1]
         self.queue: collections.deque = collections.deque()
         self.inflight: Dict[int, tuple] = {}
@@ -100,7 +157,7 @@ class SchedulerCore:
         of state changes (0 means the caller may idle briefly)."""
         changes = 0
         for rid in list(self.inflight):
-            handle, slot, nbytes = self.inflight[rid]
+            handle, slot, nbytes, off = self.inflight[rid]
             try:
                 finished = self.ex.poll(handle)
                 err = ""
@@ -109,6 +166,7 @@ class SchedulerCore:
             if finished:
                 del self.inflight[rid]
                 self.ex.release(handle)
+                self.pool.release(off, nbytes)
                 self.bytes_in_flight -= nbytes
                 self.free_slots.append(slot)
                 self._finish(rid, now, "failed" if err else "ok", err)
@@ -116,29 +174,33 @@ class SchedulerCore:
         while self.queue and self.free_slots:
             req = self.queue[0]
             need = int(self.ex.bytes_needed(req))
-            if need > self.budget:
+            if not self.pool.fits(need):
                 self.queue.popleft()
                 self._finish(req.rid, now, "rejected", "needs %d bytes, budget %d" % (need, self.budget))
                 changes += 1
                 continue
-            if self.bytes_in_flight + need > self.budget:
+            off = self.pool.alloc(need)
+            if off is None:
                 break  # FIFO: the head waits for memory, nothing overtakes it
             self.queue.popleft()
             slot = self.free_slots.pop()
             rec = self.records[req.rid]
             rec.t_admit, rec.slot, rec.nbytes = now, slot, need
             try:
-                handle = self.ex.submit(req, slot)
+                handle = self.ex.submit(req, slot, off)
             except Exception as e:  # noqa: BLE001
                 self.free_slots.append(slot)
+                self.pool.release(off, need)
                 self._finish(req.rid, now, "failed", repr(e))
                 changes += 1
                 continue
-            self.inflight[req.rid] = (handle, slot, need)
+            self.inflight[req.rid] = (handle, slot, need, off)
             self.bytes_in_flight += need
             self.peak_bytes = max(self.peak_bytes, self.bytes_in_flight)
             changes += 1
-        self.depth_log.append((now, len(self.queue), len(self.inflight), self.bytes_in_flight))
+        state = (len(self.queue), len(self.inflight), self.bytes_in_flight)
+        if not self.depth_log or self.depth_log[-1][1:] != state:
+            self.depth_log.append((now,) + state)
         return changes
 
     @property
@@ -201,99 +263,161 @@ def poisson_alg_bytes(n: int, prec: str) -> float:
 
 
 class GpuPoissonExecutor:
-    def __init__(self, sizes: Sequence[int], precs: Sequence[str], slots: int, variants: int = 2,
+    """Device side of the server: resident plans, one stream per slot and the
+    budget pool.  A request's pool range holds [f | u | ws]: its right-hand
+    side (drawn on the device), its solution and the Poisson workspace."""
+
+    ALIGN = 256
+
+    def __init__(self, sizes: Sequence[int], precs: Sequence[str], slots: int, budget_bytes: int,
                  seed: int = 0, device: str = "cuda:0"):
         import torch
 
-        from . import synth
         from .fft import Plan
         self.torch = torch
         self.device = device
+        self.seed = seed
         self.plans: Dict[tuple, Plan] = {}
-        self.rhs: Dict[tuple, list] = {}
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
         for n in sizes:
             for prec in precs:
-                p = Plan((n, n, n), "r2c", prec)
-                self.plans[(n, prec)] = p
-                dt = torch.float32 if prec == "fp32" else torch.float64
-                self.rhs[(n, prec)] = [synth.poisson_rhs_torch(n, seed * 1000 + 17 * n + v, dt, device)
-                                       for v in range(variants)]
-        # one arena per slot: output (256-byte aligned) + workspace of the largest request
-        self.arena_bytes = max(self._layout(n, prec)[2] for (n, prec) in self.plans)
-        self.arenas = [torch.empty(self.arena_bytes, dtype=torch.uint8, device=device) for _ in range(slots)]
+                self.plans[(n, prec)] = Plan((n, n, n), "r2c", prec)
+        # the budget: one pool, allocated once (sub-ranges per request)
+        self.pool = torch.empty(int(budget_bytes) // self.ALIGN * self.ALIGN, dtype=torch.uint8, device=device)
+        nmax = max(sizes)
+        # per-slot pinned staging of the generator's per-axis factors (a slot's
+        # next request starts only after its previous one has completed)
+        self.staging = [torch.empty(3 * 8 * nmax, dtype=torch.complex128, pin_memory=True) for _ in range(slots)]
         self.events = [torch.cuda.Event() for _ in range(slots)]
-        # warm-up: every plan once, so kernels are loaded before serving
-        # starts, and one solve and one event on every slot's stream (the
-        # first use of a stream sets it up, which took tens of milliseconds)
-        for (n, prec), p in self.plans.items():
-            u, ws = self._views(0, n, prec)
-            p.poisson(self.rhs[(n, prec)][0], out=u, ws=ws)
-        n_min, p_min = min(self.plans.items(), key=lambda kv: kv[0][0] ** 3)
+        self.outputs: Dict[int, object] = {}
+        self.inputs: Dict[int, object] = {}
+        self.keep_outputs = False
+        # warm-up: every plan and right-hand-side shape once (kernels and the
+        # generator's library routines load on first use), and one solve and
+        # one event on every slot's stream (the first use of a stream sets it
+        # up, which took tens of milliseconds)
+        for (n, prec), p in sorted(self.plans.items(), key=lambda kv: kv[0][0]):
+            if self.bytes_for(n, prec) > self.pool.numel():
+                continue
+            f, u, ws = self._views(0, n, prec)
+            self._draw(f, 0, self.streams[0], 0)
+            p.poisson(f, out=u, ws=ws, stream=self.streams[0])
+            torch.cuda.synchronize()
+        small = min(k for k in self.plans if self.bytes_for(*k) <= self.pool.numel())
         for slot, s in enumerate(self.streams):
-            u, ws = self._views(slot, *n_min)
-            p_min.poisson(self.rhs[n_min][0], out=u, ws=ws, stream=s)
+            f, u, ws = self._views(0, *small)
+            self._draw(f, 0, s, slot)
+            self.plans[small].poisson(f, out=u, ws=ws, stream=s)
             self.events[slot].record(s)
             self.events[slot].query()
-        torch.cuda.synchronize()
-        self.outputs: Dict[int, object] = {}
-        self.keep_outputs = False
+            torch.cuda.synchronize()
 
-    def _layout(self, n: int, prec: str):
+    def _rnd(self, b: int) -> int:
+        return -(-b // self.ALIGN) * self.ALIGN
+
+    def bytes_for(self, n: int, prec: str) -> int:
         esz = 4 if prec == "fp32" else 8
-        u_bytes = n ** 3 * esz
-        ws_off = (u_bytes + 255) // 256 * 256
-        return u_bytes, ws_off, ws_off + self.plans[(n, prec)].poisson_ws_bytes
+        return 2 * self._rnd(n ** 3 * esz) + self._rnd(self.plans[(n, prec)].poisson_ws_bytes)
 
-    def _views(self, slot: int, n: int, prec: str):
+    def _views(self, off: int, n: int, prec: str):
         torch = self.torch
-        u_bytes, ws_off, end = self._layout(n, prec)
-        a = self.arenas[slot]
+        esz = 4 if prec == "fp32" else 8
+        fb = self._rnd(n ** 3 * esz)
         dt = torch.float32 if prec == "fp32" else torch.float64
-        return a[:u_bytes].view(dt).view(n, n, n), a[ws_off:end]
+        a = self.pool
+        f = a[off:off + n ** 3 * esz].view(dt).view(n, n, n)
+        u = a[off + fb:off + fb + n ** 3 * esz].view(dt).view(n, n, n)
+        ws = a[off + 2 * fb:off + 2 * fb + self.plans[(n, prec)].poisson_ws_bytes]
+        return f, u, ws
+
+    def _draw(self, f, rid: int, stream, slot: int) -> None:
+        from . import synth
+        synth.poisson_rhs_device(f, self.rhs_seed(rid), stream=stream, staging=self.staging[slot])
+
+    def rhs_seed(self, rid: int) -> int:
+        return self.seed * 1000003 + rid
 
     def bytes_needed(self, req: Request) -> int:
-        return self._layout(req.n, req.prec)[2]
+        return self.bytes_for(req.n, req.prec)
 
-    def submit(self, req: Request, slot: int):
+    def submit(self, req: Request, slot: int, offset: int):
         p = self.plans[(req.n, req.prec)]
-        f = self.rhs[(req.n, req.prec)][req.variant % len(self.rhs[(req.n, req.prec)])]
         s = self.streams[slot]
-        u, ws = self._views(slot, req.n, req.prec)
+        f, u, ws = self._views(offset, req.n, req.prec)
+        self._draw(f, req.rid, s, slot)
         p.poisson(f, out=u, ws=ws, stream=s)
         ev = self.events[slot]
         ev.record(s)
-        return (req, ev, u, ws, slot)
+        return (req, ev, f, u, slot)
 
     def poll(self, handle) -> bool:
         return handle[1].query()
 
     def release(self, handle) -> None:
-        req, ev, u, ws, _ = handle
+        req, ev, f, u, slot = handle
         if self.keep_outputs:
-            # the slot's arena is reused by the next request: copy the output
-            # on the slot's stream, ahead of that request's work
-            with self.torch.cuda.stream(self.streams[handle[4]]):
+            # copies for the caller (tests), finished before the pool range
+            # is handed to the next request
+            s = self.streams[slot]
+            with self.torch.cuda.stream(s):
                 self.outputs[req.rid] = u.clone()
+                self.inputs[req.rid] = f.clone()
+            s.synchronize()
+
+    def run_alone(self, req: Request):
+        """The same request on an otherwise idle device (offset 0 of the
+        pool, slot 0); returns copies of (f, u)."""
+        self.torch.cuda.synchronize()
+        h = self.submit(req, 0, 0)
+        h[1].synchronize()
+        out = (h[2].clone(), h[3].clone())
+        self.torch.cuda.synchronize()
+        return out
 
     def close(self):
         for p in self.plans.values():
             p.close()
 
 
+def timeline(depth_log, points: int = 24):
+    """The scheduler's state over the replay, resampled at `points` equal
+    steps: (t_s, queue depth, requests in flight, bytes in flight)."""
+    if not depth_log:
+        return []
+    t_end = depth_log[-1][0]
+    out, k = [], 0
+    for i in range(points):
+        t = t_end * i / max(1, points - 1)
+        while k + 1 < len(depth_log) and depth_log[k + 1][0] <= t:
+            k += 1
+        out.append((round(t, 4),) + tuple(depth_log[k][1:]))
+    return out
+
+
+def mean_queue_depth(depth_log) -> float:
+    """Time-weighted mean number of waiting requests."""
+    if len(depth_log) < 2:
+        return 0.0
+    area = sum((depth_log[i + 1][0] - depth_log[i][0]) * depth_log[i][1] for i in range(len(depth_log) - 1))
+    span = depth_log[-1][0] - depth_log[0][0]
+    return area / span if span > 0 else 0.0
+
+
 def serve(n_requests: int = 2000, rate: float = 200.0, seed: int = 0, sizes=(64, 128, 256, 384, 512),
-          slots: int = 4, budget_gb: float = 32.0, keep_outputs: bool = False):
+          slots: int = 4, budget_gb: float = 16.0, keep_outputs: bool = False, schedule=None):
     """Run the open-loop Poisson-solve workload on the GPU; returns
-    (summary, records, executor)."""
+    (summary, records, executor).  `schedule` (a list of (t, n, prec))
+    replaces the drawn arrival schedule when given."""
     import torch
 
     from . import synth
-    sched = synth.arrival_schedule(n_requests, rate, seed=seed, sizes=sizes)
+    sched = schedule if schedule is not None else synth.arrival_schedule(n_requests, rate, seed=seed, sizes=sizes)
     reqs = [Request(i, t, n, prec, variant=i) for i, (t, n, prec) in enumerate(sched)]
     precs = sorted({r.prec for r in reqs})
-    ex = GpuPoissonExecutor(sorted({r.n for r in reqs}), precs, slots, seed=seed)
+    budget = int(budget_gb * 2 ** 30)
+    ex = GpuPoissonExecutor(sorted({r.n for r in reqs}), precs, slots, budget, seed=seed)
     ex.keep_outputs = keep_outputs
-    core = SchedulerCore(ex, int(budget_gb * 2 ** 30), slots)
+    core = SchedulerCore(ex, budget, slots)
     # The replay must not pause for the garbage collector: a full collection
     # over the interpreter's objects (torch's included) took ~33 ms and landed
     # on the first requests.  Collect once, move everything alive to the
@@ -312,9 +436,14 @@ def serve(n_requests: int = 2000, rate: float = 200.0, seed: int = 0, sizes=(64,
             gc.enable()
         gc.unfreeze()
     summary = summarize(recs, wall, lambda r: poisson_alg_bytes(r.n, r.prec))
-    summary.update({"slots": slots, "budget_GB": budget_gb, "rate_req_s": rate,
+    waited = [r.t_admit - r.t_arrival for r in recs.values() if r.status == "ok"]
+    summary.update({"slots": slots, "budget_GB": budget_gb, "rate_req_s": rate if schedule is None else None,
                     "peak_bytes_in_flight": core.peak_bytes,
-                    "max_queue_depth": max(d[1] for d in core.depth_log) if core.depth_log else 0})
+                    "max_queue_depth": max(d[1] for d in core.depth_log) if core.depth_log else 0,
+                    "mean_queue_depth": mean_queue_depth(core.depth_log),
+                    "queued_requests": sum(1 for w in waited if w > 1e-3),
+                    "max_admission_wait_ms": max(waited) * 1e3 if waited else math.nan,
+                    "timeline_t_queue_inflight_bytes": timeline(core.depth_log)})
     return summary, recs, ex
 
 
@@ -324,7 +453,7 @@ if __name__ == "__main__":
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--budget-gb", type=float, default=32.0)
+    ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args()
     s, _, ex = serve(a.requests, a.rate, a.seed, slots=a.slots, budget_gb=a.budget_gb)

@@ -20,6 +20,9 @@ draws rounded to nearest):
                        modes are returned too so a closed form can be checked
 * ``arrival_schedule`` exponential inter-arrival times at a given rate, grid
                        size uniform over the five sizes, float32 w.p. 0.8
+* ``poisson_rhs_device`` the Poisson right-hand side recipe written into a
+                       caller's device array (the served requests draw theirs
+                       this way, one seed per request)
 """
 from __future__ import annotations
 
@@ -148,3 +151,60 @@ def poisson_rhs_torch(n: int, seed: int, dtype, device, noise: float = 0.01):
         g.manual_seed(int(seed))
         out += noise * torch.randn((n, n, n), generator=g, dtype=torch.float64, device=device)
     return out.to(dtype)
+
+
+def poisson_rhs_device(out, seed: int, noise: float = 0.01, stream=None, staging=None):
+    """The Poisson right-hand side recipe written into the device array
+    ``out`` (n x n x n, float32 or float64) on ``stream``: the 8 modes of
+    ``poisson_modes(n, seed)`` plus N(0, noise^2) noise from a torch device
+    generator seeded with ``seed`` (``mode_sum_device``).  The values depend
+    only on (n, seed, dtype)."""
+    ks, amp, phase, _ = poisson_modes(out.shape[0], seed)
+    return mode_sum_device(out, ks, amp, phase, noise=noise, seed=seed, stream=stream, staging=staging)
+
+
+def mode_sum_device(out, ks, amp, phase, noise: float = 0.0, seed: int = 0, stream=None, staging=None):
+    """sum_j amp_j cos(k_j . x + phase_j) (the ``mode_sum`` grid) plus
+    N(0, noise^2) noise, written into the device array ``out`` (n x n x n,
+    float32 or float64) on ``stream``.  The sum is separable,
+    cos(a + b + c) = Re(e^{ia} e^{ib} e^{ic}), so it is evaluated as one
+    matrix product: out[(x, y), z] += sum_j Re(A_j[x, y] E_j[z]) with
+    A_j = amp_j e^{i phase_j} e^{i kx_j x} e^{i ky_j y} and E_j = e^{i kz_j z}
+    (real and imaginary parts as a rank-2J product), after the noise (from a
+    torch device generator seeded with ``seed``) is drawn into ``out``.  The
+    per-axis factors are built on the host in float64 and copied in (through
+    ``staging``, a pinned complex128 host tensor of at least 3 J n elements,
+    when given, so the copy does not block the caller; it must not be reused
+    before this stream's work is done)."""
+    import torch
+    n = out.shape[0]
+    ks = np.asarray(ks, dtype=np.int64)
+    amp = np.asarray(amp, dtype=np.float64)
+    phase = np.asarray(phase, dtype=np.float64)
+    J = len(amp)
+    x = 2.0 * np.pi * np.arange(n, dtype=np.float64) / n
+    ex = np.exp(1j * (ks[:, 0:1] * x[None, :] + phase[:, None])) * amp[:, None]   # (J, n)
+    ey = np.exp(1j * ks[:, 1:2] * x[None, :])                                      # (J, n)
+    ez = np.exp(1j * ks[:, 2:3] * x[None, :])                                      # (J, n)
+    dt = out.dtype
+    s = torch.cuda.current_stream(out.device) if stream is None else stream
+    with torch.cuda.stream(s):
+        host = np.stack([ex, ey, ez])
+        if staging is not None:
+            st = staging[:3 * J * n].view(3, J, n)
+            st.copy_(torch.from_numpy(host))
+            tab = st.to(out.device, non_blocking=True)
+        else:
+            tab = torch.from_numpy(host).to(out.device)
+        a = tab[0][:, :, None] * tab[1][:, None, :]                                # (J, n, n)
+        lhs = torch.cat([a.real, -a.imag]).reshape(2 * J, n * n).to(dt)            # (2J, n^2)
+        rhs = torch.cat([tab[2].real, tab[2].imag]).to(dt)                         # (2J, n)
+        f2 = out.view(n * n, n)
+        if noise:
+            g = torch.Generator(device=out.device)
+            g.manual_seed(int(seed))
+            f2.normal_(0.0, noise, generator=g)
+        else:
+            f2.zero_()
+        f2.addmm_(lhs.t(), rhs)
+    return out

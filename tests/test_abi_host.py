@@ -194,6 +194,8 @@ def test_batch_argument_validation(L):
     assert L.mifft_batch_create(C.byref(h), 2, dims, 1, 0, 0) == 2      # R2C batches not offered
     assert L.mifft_batch_create(C.byref(h), 2, dims, 0, 0, 0x100) == 1  # unknown flag
     assert L.mifft_batch_create(C.byref(h), 2, dims, 0, 0, 4 | 8) == 1   # kernels and grouped
+    assert L.mifft_batch_create(C.byref(h), 2, dims, 0, 0, 1) == 2       # MIFFT_TUNE: not persistent
+    assert b"MIFFT_TUNE" in L.mifft_last_error()
     big = (C.c_int * 6)(512, 64, 64, 48, 48, 48)
     assert L.mifft_batch_create(C.byref(h), 2, big, 0, 0, 0) == 2       # 512 not in the menu
     assert L.mifft_batch_create(C.byref(h), 129, (C.c_int * 387)(*([8] * 387)), 0, 0, 0) == 2
@@ -205,3 +207,32 @@ def test_batch_argument_validation(L):
     assert L.mifft_batch_destroy(bogus) == 5
     flag = C.c_int()
     assert L.mifft_batch_check(bogus, C.byref(flag)) == 5
+
+
+def test_reference_copies_reject_out_of_range_patterns(L):
+    """The measurement copies check every offset against the caller's sizes
+    on the host, before any launch (the pointers here are never touched)."""
+    a, b = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x40000000)
+    L_, cols, groups, es, gs = 40, 45, 3, 48, 48 * 40
+    need_in = (groups - 1) * gs + (cols - 1) + (L_ - 1) * es + 1
+    es_o, gs_o = 3 * 45, 45
+    need_out = (groups - 1) * gs_o + (cols - 1) + (L_ - 1) * es_o + 1
+    f = L.mifft_pattern_copy
+    assert f(0, a, need_in - 1, b, need_out, L_, cols, groups, es, es_o, gs, gs_o, 16, 8, 0, None) == 1
+    assert b"reaches" in L.mifft_last_error()
+    assert f(0, a, need_in, b, need_out - 1, L_, cols, groups, es, es_o, gs, gs_o, 16, 8, 0, None) == 1
+    # huge strides cannot wrap around the size check
+    assert f(0, a, 1 << 40, b, 1 << 40, 1024, 1, 2, 1 << 62, 1, 1 << 62, 1, 1, 1, 0, None) == 1
+    assert f(0, a, need_in, a, need_out, L_, cols, groups, es, es_o, gs, gs_o, 16, 8, 0, None) == 1  # overlap
+    assert f(0, a, need_in, b, need_out, L_, cols, groups, es, es_o, gs, gs_o, 16, 8, 4, None) == 1  # flags
+    assert f(0, a, need_in, b, need_out, L_, cols, groups, es, es_o, gs, gs_o, 64, 32, 0, None) == 1  # 2048 threads
+    assert f(0, a, need_in, b, need_out, L_, cols, groups, -1, es_o, gs, gs_o, 16, 8, 0, None) == 1
+    assert f(0, None, need_in, b, need_out, L_, cols, groups, es, es_o, gs, gs_o, 16, 8, 0, None) == 1
+    assert f(0, ctypes.c_void_p(0x100004), need_in, b, need_out, L_, cols, groups, es, es_o, gs, gs_o,
+             16, 8, 0, None) == 1                                                              # misaligned
+    g = L.mifft_copy_reference
+    assert g(a, ctypes.c_void_p(0x100000 + 4096), 8192, 0, 0, None) == 1       # overlap
+    assert g(a, b, 100, 0, 0, None) == 1                                        # not a multiple of 16
+    assert g(a, b, 4096, 8, 0, None) == 1                                       # flags
+    assert g(a, b, 4096, 0, -1, None) == 1                                      # grid
+    assert g(None, b, 4096, 0, 0, None) == 1

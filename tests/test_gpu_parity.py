@@ -262,6 +262,80 @@ def test_poisson_solve(prec, n):
     p.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [384, 512])
+def test_poisson_solve_largest_served_sizes(prec, n):
+    """The two largest served sizes: the fused spectral x-pass at L = 384 and
+    512, the y-passes over padded half-spectrum rows (pitch 208 / 272 / 264
+    complex elements), the 384- and 512-point R2C / C2R z-passes.  The
+    right-hand side (Poisson recipe) is drawn on the device and copied back
+    for the oracle; a noise-free mode sum is checked against the closed form
+    (itself evaluated in FP64 on the device)."""
+    from paper_1506_07933_amd import Plan
+    p = Plan((n, n, n), "r2c", prec)
+    for line in p.describe().splitlines():
+        if line.startswith("poisson"):
+            print("   ", " ".join(w for w in line.split() if w.split("=")[0] in
+                              ("kind", "axis", "L", "tpl", "B", "es", "gs", "block", "shmem")), flush=True)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    f = torch.empty((n, n, n), dtype=dt, device=DEV)
+    synth.poisson_rhs_device(f, seed=n)
+    u = host(p.poisson(f))
+    ref = oracle.poisson_solve(host(f).astype(np.float64))
+    report("poisson %s n=%d vs oracle" % (prec, n), rel_l2(u, ref), TOL[prec])
+    del u, ref
+    ks, amp, ph, _ = synth.poisson_modes(n, n)
+    f0 = torch.empty_like(f)
+    synth.mode_sum_device(f0, ks, amp, ph)
+    u0 = p.poisson(f0)
+    ref0 = torch.empty((n, n, n), dtype=torch.float64, device=DEV)
+    synth.mode_sum_device(ref0, ks, -amp / np.sum(ks * ks, axis=1), ph)
+    report("poisson %s n=%d vs closed form" % (prec, n), rel_l2(host(u0), host(ref0)),
+           1e-12 if prec == "fp64" else 5e-6)
+    p.close()
+
+
+def test_r2c_c2r_512cube_fp32():
+    """512^3 real N(0,1) through the FP32 R2C plan: the 256-point half-length
+    z-lines, the padded transposed intermediate (rows of 272), the
+    flattened-tile x-pass into the 512 x 512 x 257 spectrum, and C2R back."""
+    from paper_1506_07933_amd import Plan
+    x = synth.normal_real((512, 512, 512), np.float32, seed=0)
+    p = Plan(x.shape, "r2c", "fp32")
+    xd = gpu(x)
+    Y = p.forward(xd)
+    assert tuple(Y.shape) == (512, 512, 257)
+    Yh = host(Y)
+    x64 = x.astype(np.float64)
+    report("512^3 r2c fp32 vs oracle", rel_l2(Yh, oracle.fft3d_r2c(x64)), 5e-6)
+    xr = host(p.inverse(Y))
+    np.testing.assert_array_equal(host(Y), Yh)     # C2R preserves its input
+    del Yh
+    report("512^3 c2r(r2c(x)) fp32", rel_l2(xr, float(512 ** 3) * x64), 5e-6)
+    p.close()
+
+
+def test_laplacian_512cube_fp32():
+    """The spectral Laplacian at 512^3 FP32 (the fused x-pass with the
+    Laplacian multiplier): against the oracle on the Poisson recipe's field,
+    and against the closed form on a noise-free mode sum."""
+    from paper_1506_07933_amd import Plan
+    n = 512
+    p = Plan((n, n, n), "r2c", "fp32")
+    f = torch.empty((n, n, n), dtype=torch.float32, device=DEV)
+    synth.poisson_rhs_device(f, seed=7)
+    u = host(p.spectral(oracle.OP_LAPLACIAN, f))
+    report("512^3 fp32 Laplacian vs oracle",
+           rel_l2(u, oracle.spectral_apply(host(f).astype(np.float64), oracle.OP_LAPLACIAN)), 5e-6)
+    ks, amp, ph, _ = synth.poisson_modes(n, 7)
+    synth.mode_sum_device(f, ks, amp, ph)
+    ref = torch.empty((n, n, n), dtype=torch.float64, device=DEV)
+    synth.mode_sum_device(ref, ks, -amp * np.sum(ks * ks, axis=1), ph)
+    report("512^3 fp32 Laplacian vs closed form", rel_l2(host(p.spectral(oracle.OP_LAPLACIAN, f)), host(ref)),
+           5e-6)
+    p.close()
+
+
 @pytest.mark.parametrize("prec,shape", [("fp64", (256, 256, 256)), ("fp32", (256, 256, 256)),
                                         ("fp64", (64, 48, 32)), ("fp32", (96, 1, 64)),
                                         ("fp64", (2, 3, 4)), ("fp32", (1, 16, 8))])
@@ -365,14 +439,24 @@ def test_pattern_copy_reference_kernel():
     src = synth.uniform_complex((groups * gs_in,), np.complex64, seed=11)
     a = gpu(src)
     b = torch.zeros(L * es_out, dtype=torch.complex64, device=DEV)
-    assert lib.mifft_pattern_copy(0, a.data_ptr(), b.data_ptr(), L, cols, groups, es_in, es_out, gs_in, gs_out,
-                                  16, 8, None) == 0
-    got = host(b)
     want = np.zeros(L * es_out, dtype=np.complex64)
     for g in range(groups):
         for r in range(L):
             want[g * gs_out + r * es_out: g * gs_out + r * es_out + cols] = \
                 src[g * gs_in + r * es_in: g * gs_in + r * es_in + cols]
-    np.testing.assert_array_equal(got, want)
-    assert lib.mifft_pattern_copy(0, a.data_ptr(), a.data_ptr(), L, cols, groups, es_in, es_out, gs_in, gs_out,
-                                  16, 8, None) == 1
+    for flags in (0, 1, 2, 3):          # cached / streaming loads and stores
+        b.zero_()
+        assert lib.mifft_pattern_copy(0, a.data_ptr(), a.numel(), b.data_ptr(), b.numel(), L, cols, groups,
+                                      es_in, es_out, gs_in, gs_out, 16, 8, flags, None) == 0
+        np.testing.assert_array_equal(host(b), want)
+    # one element short of what the pattern reaches: rejected before any launch
+    assert lib.mifft_pattern_copy(0, a.data_ptr(), a.numel(), b.data_ptr(), b.numel() - 1, L, cols, groups,
+                                  es_in, es_out, gs_in, gs_out, 16, 8, 0, None) == 1
+    assert lib.mifft_pattern_copy(0, a.data_ptr(), a.numel(), a.data_ptr(), a.numel(), L, cols, groups, es_in,
+                                  es_out, gs_in, gs_out, 16, 8, 0, None) == 1
+    # the contiguous reference copy, every load / store flavour, ragged grid
+    c = torch.empty_like(a)
+    for flags in (0, 1, 2, 3):
+        c.zero_()
+        assert lib.mifft_copy_reference(a.data_ptr(), c.data_ptr(), a.numel() * 8, flags, 3, None) == 0
+        np.testing.assert_array_equal(host(c), src)

@@ -149,7 +149,55 @@ def test_plan_only_cannot_execute():
     buf = ctypes.c_void_p(0x10000)
     assert lib.mifft_execute_forward(h, buf, buf, None) == 5
     assert lib.mifft_plan_destroy(h) == 0
-    assert lib.mifft_plan_create(ctypes.byref(h), 8, 8, 8, 0, 0, MIFFT_PLAN_ONLY | 1) == 1
+    assert lib.mifft_plan_create(ctypes.byref(h), 8, 8, 8, 0, 0, MIFFT_PLAN_ONLY | 4) == 1
+
+
+_WISDOM_CHILD = r"""
+import ctypes, sys
+from paper_1506_07933_amd._lib import MIFFT_PLAN_ONLY, lib
+from paper_1506_07933_amd.fft import plan_describe, plan_destroy
+h = ctypes.c_void_p()
+assert lib.mifft_plan_create(ctypes.byref(h), 64, 64, 64, 0, 0, MIFFT_PLAN_ONLY | 1) == 0, lib.mifft_last_error()
+print(plan_describe(h.value))
+plan_destroy(h.value)
+"""
+
+
+def test_wisdom_only_plan_applies_valid_entries_and_ignores_malformed(tmp_path):
+    """MIFFT_TUNE with MIFFT_PLAN_ONLY applies stored choices without a device.
+    A strided tile width must be a power of two (the kernel maps threads to
+    columns with a mask): B = 24 or B = 0 in a hand-edited file is ignored
+    and the heuristic shape stays."""
+    import os
+    import subprocess
+    import sys
+    passes, _, _ = plan_only(64, 64, 64)
+    y = [d for d in passes if d["dir"] == "forward" and d["axis"] == "y"][0]
+    x = [d for d in passes if d["dir"] == "forward" and d["axis"] == "x"][0]
+    z = [d for d in passes if d["dir"] == "forward" and d["axis"] == "z"][0]
+
+    def key(d):
+        return "gfx950|fp32|strided|L=64|cols=%s|groups=%s|es=%s|gs=%s" % (d["cols"], d["groups"], d["es"], d["gs"])
+
+    assert int(y["B"]) != 8 and int(x["B"]) == int(y["B"])
+    wis = tmp_path / "wisdom.json"
+    wis.write_text("{\n"
+                   '  "%s": [0, 1, 8, 0, 1.0],\n' % key(y) +          # valid: B = 8
+                   '  "%s": [0, 1, 24, 0, 1.0],\n' % key(x) +         # not a power of two
+                   '  "gfx950|fp32|contig|L=64|lines=%s": [0, 1, 0, 0, 1.0]\n' % z["lines"] +  # lpw 0
+                   "}\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, MIFFT_WISDOM=str(wis), PYTHONPATH=root)
+    out = subprocess.run([sys.executable, "-c", _WISDOM_CHILD], env=env, cwd=root,
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    got = [dict(kv.split("=") for kv in l.split()[1:]) | {"dir": l.split()[0]}
+           for l in out.stdout.splitlines() if l.startswith(("forward", "inverse"))]
+    gy = [d for d in got if d["dir"] == "forward" and d["axis"] == "y"][0]
+    gx = [d for d in got if d["dir"] == "forward" and d["axis"] == "x"][0]
+    gz = [d for d in got if d["dir"] == "forward" and d["axis"] == "z"][0]
+    assert int(gy["B"]) == 8 and int(gy["block"]) == 8 * int(gy["tpl"])
+    assert gx["B"] == x["B"] and gz["lpw"] == z["lpw"]
 
 
 def test_pencil_plan_only_describes_fused_stages():
