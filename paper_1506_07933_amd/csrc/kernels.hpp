@@ -477,8 +477,6 @@ template <typename T> struct PoissonXArgs {
     const cx<T>* src;
     cx<T>* data;
     const cx<T>* tw;
-    int B;
-    int log2B;
     int cols;
     int groups;
     int tpg; // as in StridedArgs
@@ -493,8 +491,10 @@ template <typename T> struct PoissonXArgs {
 // inverse) back into the LDS tile -- safe, because every stage after the
 // first synchronises between reading its inputs from the tile and writing.
 // PHASE 1: the inverse transform (of the conjugate) reads the line from LDS
-// and stores the conjugate of its result.
-template <typename T, int PHASE> struct PoissonCtx {
+// and stores the conjugate of its result.  B (columns per tile) is a
+// compile-time constant, so the LDS offsets of a thread's elements are
+// constants from one base address.
+template <typename T, int PHASE, int B> struct PoissonCtx {
     using V = cx<T>;
     static constexpr bool kSyncAfterFirstRead = PHASE == 1; // the first stage reads the LDS tile
     const V* src;
@@ -502,7 +502,6 @@ template <typename T, int PHASE> struct PoissonCtx {
     V* lds; // column c of the tile: element idx at lds[idx * B]
     const V* twd;
     int t;
-    int B;
     bool valid;
     long long es;
     // PHASE 0: the multiplier
@@ -543,29 +542,56 @@ template <typename T, int PHASE> struct PoissonCtx {
     __device__ __forceinline__ void sync() const { __syncthreads(); }
 };
 
+// Tile shape of the fused spectral x-pass for (T, L, TPL).  A workgroup
+// loads its tile, runs two transforms on it and stores it, so a CU whose
+// only workgroup is in its transforms has no memory traffic; the tile is
+// therefore the widest (at most 256-byte rows) that lets two workgroups
+// share a CU's 160 KiB of LDS, and the kernel is compiled for the register
+// budget of two resident workgroups.  Measured on the 512^3 FP32 solve's
+// x-pass: 32 columns, one workgroup per CU, 355 us; 16 columns of 64
+// threads each, two per CU, 266 us (FP64: 16 -> 8 columns, 609 -> 517 us).
+template <typename T, int L, int TPL> constexpr int poisson_tile_B()
+{
+    int b = 256 / (int)sizeof(cx<T>);
+    while (b > 1 && (b * TPL > 1024 || (size_t)(b + 1) * L * sizeof(cx<T>) > 80 * 1024)) b /= 2;
+    return b;
+}
+// Waves per SIMD the register allocation must allow: two workgroups per CU
+// (four SIMDs), at least four (the budget of a 1024-thread workgroup) and,
+// in FP64, at most four (at 64 registers the FP64 972-point kernel spilled).
+template <typename T, int L, int TPL> constexpr int poisson_waves()
+{
+    const int waves = (poisson_tile_B<T, L, TPL>() * TPL + 63) / 64;
+    const int w = (2 * waves + 3) / 4;
+    const int cap = sizeof(T) == 8 ? 4 : 8;
+    return w < 4 ? 4 : (w > cap ? cap : w);
+}
+
 template <typename T, int L, int P, int TPL>
-__global__ __launch_bounds__(1024) void k_strided_poisson(PoissonXArgs<T> a)
+__global__ __launch_bounds__((poisson_tile_B<T, L, TPL>() * TPL),
+                             (poisson_waves<T, L, TPL>())) void k_strided_poisson(PoissonXArgs<T> a)
 {
     using V = cx<T>;
     using RLt = typename RL<L, P>::type;
+    constexpr int B = poisson_tile_B<T, L, TPL>();
     extern __shared__ unsigned char smem_raw[];
     V* smem = reinterpret_cast<V*>(smem_raw);
     const int tid = threadIdx.x;
-    const int cc = tid & (a.B - 1);
-    const int t = tid >> a.log2B;
+    const int cc = tid & (B - 1);
+    const int t = tid / B;
     // tiles as in k_strided
     int g, col;
     if (a.tpg > 0) {
         g = (int)blockIdx.x / a.tpg;
-        col = ((int)blockIdx.x - g * a.tpg) * a.B + cc;
+        col = ((int)blockIdx.x - g * a.tpg) * B + cc;
         if (col >= a.cols) g = a.groups; // padding column of a ragged tile
     } else {
-        const unsigned f = (unsigned)blockIdx.x * (unsigned)a.B + (unsigned)cc;
+        const unsigned f = (unsigned)blockIdx.x * (unsigned)B + (unsigned)cc;
         g = (int)(f / (unsigned)a.cols);
         col = (int)(f - (unsigned)g * (unsigned)a.cols);
     }
-    const V* twd = stage_twiddles<T>(a.tw, L, smem + a.B * L);
-    PoissonCtx<T, 0> c0;
+    const V* twd = stage_twiddles<T>(a.tw, L, smem + B * L);
+    PoissonCtx<T, 0, B> c0;
     c0.valid = g < a.groups;
     const long long off = (long long)g * a.gs + col;
     c0.src = a.src + off;
@@ -573,7 +599,6 @@ __global__ __launch_bounds__(1024) void k_strided_poisson(PoissonXArgs<T> a)
     c0.lds = smem + cc;
     c0.twd = twd;
     c0.t = t;
-    c0.B = a.B;
     c0.es = a.es;
     c0.n0 = L;
     c0.op = a.op;
@@ -582,14 +607,13 @@ __global__ __launch_bounds__(1024) void k_strided_poisson(PoissonXArgs<T> a)
     c0.alpha = a.alpha;
     LineFFT<T, L, TPL, decltype(c0), RLt>::run(c0);
     __syncthreads(); // the multiplied spectrum of every column is in the tile
-    PoissonCtx<T, 1> c1;
+    PoissonCtx<T, 1, B> c1;
     c1.valid = c0.valid;
     c1.acc = a.acc != 0;
     c1.data = c0.data;
     c1.lds = c0.lds;
     c1.twd = twd;
     c1.t = t;
-    c1.B = a.B;
     c1.es = a.es;
     LineFFT<T, L, TPL, decltype(c1), RLt>::run(c1);
 }

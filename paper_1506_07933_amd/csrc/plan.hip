@@ -118,6 +118,11 @@ int variant_prefetch(int prec, int i)
     return with_table(prec, [i](const auto& t) { return t[i].prefetch; });
 }
 
+int variant_poisson_B(int prec, int i)
+{
+    return with_table(prec, [i](const auto& t) { return t[i].poisson_B; });
+}
+
 int variant_radices(int prec, int i, int* radix, int max)
 {
     return with_table(prec, [&](const auto& t) {
@@ -244,6 +249,19 @@ void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int group
     p.grid = (unsigned)p.ntiles;
     p.block = (unsigned)(B * tpl);
     p.shmem = ((size_t)B * L + L) * esz; // tile + the staged twiddle table
+}
+
+// A column tile of exactly B columns (the fused spectral x-pass's kernel is
+// compiled for one width; columns past the end of a group are idle).
+void set_tile_width(Pass& p, int prec, int tpl, int B)
+{
+    const size_t esz = prec == MIFFT_FP64 ? 16 : 8;
+    p.B = B;
+    p.log2B = ilog2(B);
+    p.ntiles = (int)(((long long)p.groups * p.cols + B - 1) / B);
+    p.grid = (unsigned)p.ntiles;
+    p.block = (unsigned)(B * tpl);
+    p.shmem = ((size_t)B * p.L + p.L) * esz; // tile + the staged twiddle table
 }
 
 // ----------------------------------------------------------------- launch
@@ -401,8 +419,6 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.src = (const V*)src;
         a.data = (V*)dst;
         a.tw = (const V*)p.tw;
-        a.B = p.B;
-        a.log2B = p.log2B;
         a.cols = p.cols;
         a.groups = p.groups;
         a.tpg = p.tpg;
@@ -1081,15 +1097,18 @@ void rebuild_poisson(Plan& plan)
             plan.poisson.push_back(y);
         }
         {
-            // fused x, in place: the forward x-pass's variant and tile shape
+            // fused x, in place: the default variant of the length (the most
+            // threads per line) and the tile width its kernel is compiled for
             Pass x;
+            int vp = default_variant(plan.prec, plan.n0);
+            if (vp < 0) vp = vx;
             if (T)
-                rc = make_strided(plan, x, plan.n0, nc, plan.n1, pitch, (long long)plan.n0 * pitch, vx, fx->B);
+                rc = make_strided(plan, x, plan.n0, nc, plan.n1, pitch, (long long)plan.n0 * pitch, vp, 1);
             else
-                rc = make_strided(plan, x, plan.n0, (int)plane, 1, plane, 0, vx, fx->B);
+                rc = make_strided(plan, x, plan.n0, (int)plane, 1, plane, 0, vp, 1);
             if (rc) goto fallback;
+            set_tile_width(x, plan.prec, variant_tpl(plan.prec, vp), variant_poisson_B(plan.prec, vp));
             x.kind = P_POISSON_X;
-            x.grid = (unsigned)x.ntiles; // one workgroup per tile
             x.n0 = plan.n0;
             x.n1 = plan.n1;
             x.n2c = pitch; // column -> (k1, k2) = (g + col / pitch, col % pitch)

@@ -127,6 +127,8 @@ int variant_tpl(int prec, int idx);
 int variant_policy(int prec, int idx);
 int variant_emul(int prec, int idx);
 int variant_prefetch(int prec, int idx);
+int variant_poisson_B(int prec, int idx);
+void set_tile_width(Pass& p, int prec, int tpl, int B);
 int variant_radices(int prec, int idx, int* radix, int max); // stage count; radices in stage order
 int find_variant(int prec, int L, int policy, int emul);
 int default_variant(int prec, int L);

@@ -18,6 +18,7 @@ template <typename T> struct Variant {
     int emul;
     int tpl;     // threads per line
     int prefetch; // the strided kernel prefetches the next column tile
+    int poisson_B; // columns per tile of the fused spectral x-pass (compiled in)
     int nstages;
     int radix[24];
     ContigFn<T> contig;

@@ -23,6 +23,7 @@ template <int L, int P, int E> constexpr Variant<MIFFT_REAL> make_variant()
     v.emul = E;
     v.tpl = TPL;
     v.prefetch = strided_prefetches<MIFFT_REAL, L, P, TPL>() ? 1 : 0;
+    v.poisson_B = poisson_tile_B<MIFFT_REAL, L, TPL>();
     v.nstages = f.n;
     for (int i = 0; i < f.n; ++i) v.radix[i] = f.r[i];
     v.contig = &k_contig<MIFFT_REAL, L, P, TPL, false>;
