@@ -150,6 +150,25 @@ int mifft_execute_inverse_ws(mifft_plan plan, const void* in, void* out, void* w
                              void* stream);
 
 /*
+ * mifft_execute_forward_static -- for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): mifft_execute_forward with its workspace in a file-scope
+ * device array of MIFFT_SCRATCH_BYTES that the library holds on every GPU
+ * it runs on until the process ends.  The call allocates nothing (no
+ * hipMalloc / hipFree, no allocating library routine); the caller passes
+ * `in` and `out` as for mifft_execute_forward.
+ *   Errors: MIFFT_ERR_INVALID when the plan's workspace
+ *   (mifft_workspace_bytes) exceeds MIFFT_SCRATCH_BYTES (checked before any
+ *   HIP call) or when the current device is not the plan's; otherwise as
+ *   mifft_execute_forward.
+ *   Concurrency: every call on one GPU shares that GPU's array, so calls
+ *   that overlap on one GPU (other streams, other threads) race; nothing in
+ *   the array needs to start at zero.
+ */
+#define MIFFT_SCRATCH_BYTES (256u << 20)
+int mifft_execute_forward_static(mifft_plan plan, const void* in, void* out, void* stream);
+
+/*
  * mifft_plan_destroy -- free the plan's device memory.  NULL is a no-op that
  * returns MIFFT_OK; a handle that is not live returns MIFFT_ERR_BADPLAN.
  */

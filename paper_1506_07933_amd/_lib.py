@@ -32,6 +32,7 @@ SIGNATURES = {
     "mifft_workspace_bytes": (_sz, [_vp]),
     "mifft_execute_forward_ws": (_i, [_vp, _cvp, _vp, _vp, _vp]),
     "mifft_execute_inverse_ws": (_i, [_vp, _cvp, _vp, _vp, _vp]),
+    "mifft_execute_forward_static": (_i, [_vp, _cvp, _vp, _vp]),
     "mifft_plan_destroy": (_i, [_vp]),
     "mifft_last_error": (ctypes.c_char_p, []),
     "mifft_plan_create_pencil": (_i, [_vpp, _i, _i, _i, _i, _i, _i, _i, _u]),

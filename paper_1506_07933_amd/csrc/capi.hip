@@ -441,6 +441,61 @@ int mifft_execute_inverse(mifft_plan plan, const void* in, void* out, void* stre
     return run_passes(*plan, plan->inv, in, out, plan->ws, nullptr, nullptr, (hipStream_t)stream);
 }
 
+// Forward transform whose workspace is the file-scope device array below
+// instead of the plan's or the caller's (for callers that cannot allocate).
+// In host code `mifft_scratch` only stands for the symbol: the device address
+// of each GPU's copy comes from hipGetSymbolAddress, taken once per device
+// (with that device current) on the first call there, and only that address
+// is ever handed to kernels.
+} // extern "C"
+
+static __device__ __align__(256) unsigned char mifft_scratch[MIFFT_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+} // namespace
+
+static int scratch_address(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return set_error(MIFFT_ERR_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(mifft_scratch));
+        if (e != hipSuccess || !ptr)
+            return set_error(MIFFT_ERR_DEVICE, "address of the static scratch array on device %d: %s", dev,
+                             hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MIFFT_OK;
+}
+
+extern "C" {
+
+int mifft_execute_forward_static(mifft_plan plan, const void* in, void* out, void* stream)
+{
+    clear_error();
+    if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");
+    if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
+    if (plan->ws_bytes > (size_t)MIFFT_SCRATCH_BYTES)
+        return set_error(MIFFT_ERR_INVALID,
+                         "this plan needs %zu bytes of workspace; the static scratch array holds %zu",
+                         plan->ws_bytes, (size_t)MIFFT_SCRATCH_BYTES);
+    int rc = check_exec(plan, in, out, nullptr, false);
+    if (rc) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "no current device");
+    if (dev != plan->device)
+        return set_error(MIFFT_ERR_INVALID, "the plan lives on device %d, the current device is %d", plan->device,
+                         dev);
+    void* ws = nullptr;
+    if (plan->ws_bytes && (rc = scratch_address(dev, &ws))) return rc;
+    return run_passes(*plan, plan->fwd, in, out, ws, nullptr, nullptr, (hipStream_t)stream);
+}
+
 static int check_spectral(mifft_plan plan, const void* ws)
 {
     if (!plan) return set_error(MIFFT_ERR_INVALID, "plan is NULL");

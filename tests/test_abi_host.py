@@ -236,3 +236,27 @@ def test_reference_copies_reject_out_of_range_patterns(L):
     assert g(a, b, 4096, 8, 0, None) == 1                                       # flags
     assert g(a, b, 4096, 0, -1, None) == 1                                      # grid
     assert g(None, b, 4096, 0, 0, None) == 1
+
+
+def test_static_scratch_entry_rejects_large_workspaces(L):
+    """The no-allocation forward transform refuses a plan whose workspace
+    exceeds the static scratch array, before any HIP call (a plan-only 512^3
+    C2C plan needs 1 GiB for its transposed intermediate)."""
+    from paper_1506_07933_amd._lib import MIFFT_C2C, MIFFT_FP32, MIFFT_PLAN_ONLY
+    p = ctypes.c_void_p()
+    assert L.mifft_plan_create(ctypes.byref(p), 512, 512, 512, MIFFT_C2C, MIFFT_FP32, MIFFT_PLAN_ONLY) == 0
+    try:
+        assert L.mifft_workspace_bytes(p) == 512 ** 3 * 8 > 256 << 20
+        a, b = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x40000000)
+        assert L.mifft_execute_forward_static(p, a, b, None) == 1
+        assert b"static scratch" in L.mifft_last_error()
+        assert L.mifft_execute_forward_static(None, a, b, None) == 1
+    finally:
+        assert L.mifft_plan_destroy(p) == 0
+    # a plan-only plan that fits is refused as any plan-only execute is
+    q = ctypes.c_void_p()
+    assert L.mifft_plan_create(ctypes.byref(q), 64, 64, 64, MIFFT_C2C, MIFFT_FP32, MIFFT_PLAN_ONLY) == 0
+    try:
+        assert L.mifft_execute_forward_static(q, ctypes.c_void_p(0x100000), ctypes.c_void_p(0x40000000), None) == 5
+    finally:
+        assert L.mifft_plan_destroy(q) == 0
