@@ -401,6 +401,7 @@ const char* mifft_version(void);
  * ranges. */
 #define MIFFT_COPY_NT_LOADS 1u
 #define MIFFT_COPY_NT_STORES 2u
+#define MIFFT_COPY_BLOCKED 4u
 int mifft_pattern_copy(int prec, const void* in, size_t in_elems, void* out, size_t out_elems, int L, int cols,
                        int groups, long long es_in, long long es_out, long long gs_in, long long gs_out, int B,
                        int threads_per_col, unsigned flags, void* stream);
@@ -409,6 +410,9 @@ int mifft_pattern_copy(int prec, const void* in, size_t in_elems, void* out, siz
  * 16-byte vector accesses, several in flight per thread, over `grid`
  * workgroups of 256 threads (0: enough for four words per thread) -- the
  * plain contiguous copy, the achievable bandwidth ceiling of the device.
+ * With MIFFT_COPY_BLOCKED each workgroup of 128 threads copies one
+ * contiguous 8 KiB block, all its loads before its stores (the grid is then
+ * the number of blocks; `grid` is ignored).
  * Both buffers hold at least `bytes` and are caller-owned.  INVALID for NULL
  * or unaligned pointers, a size not a multiple of 16, a negative grid,
  * unknown flags or overlapping ranges. */

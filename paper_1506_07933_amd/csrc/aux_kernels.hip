@@ -257,10 +257,55 @@ __global__ __launch_bounds__(256) void k_copy_ref(const uint4* __restrict__ a, u
     }
 }
 
+// Blocked reference copy: workgroup b copies the contiguous block of
+// 4 x 128 words at b x 512 (8 KiB, as one z-pass workgroup of two 512-point
+// complex64 lines reads and then writes), all four loads of a thread before
+// its stores.  The last block may be partial.
+template <bool NTL, bool NTS>
+__global__ __launch_bounds__(128) void k_copy_blk(const uint4* __restrict__ a, uint4* __restrict__ b, long long n16)
+{
+    typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+    constexpr int U = 4;
+    const long long base = (long long)blockIdx.x * (U * 128) + threadIdx.x;
+    U4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const long long i = base + u * 128;
+        if (i < n16) {
+            const U4* q = reinterpret_cast<const U4*>(a + i);
+            if constexpr (NTL)
+                v[u] = __builtin_nontemporal_load(q);
+            else
+                v[u] = *q;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const long long i = base + u * 128;
+        if (i < n16) {
+            U4* q = reinterpret_cast<U4*>(b + i);
+            if constexpr (NTS)
+                __builtin_nontemporal_store(v[u], q);
+            else
+                *q = v[u];
+        }
+    }
+}
+
 hipError_t launch_copy_ref(const void* src, void* dst, size_t bytes, unsigned flags, int grid, hipStream_t s)
 {
     const long long n16 = (long long)(bytes / 16);
     if (n16 == 0) return hipSuccess;
+    if (flags & 4u) { // blocked: one 8 KiB block per workgroup (grid ignored)
+        const long long blocks = (n16 + 511) / 512;
+        auto fb = (flags & 3u) == 3u ? k_copy_blk<true, true>
+                  : (flags & 1u)     ? k_copy_blk<true, false>
+                  : (flags & 2u)     ? k_copy_blk<false, true>
+                                     : k_copy_blk<false, false>;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(fb, dim3((unsigned)blocks), dim3(128), 0, s, (const uint4*)src, (uint4*)dst, n16);
+        return hipGetLastError();
+    }
     long long blocks = grid > 0 ? grid : (n16 + 4 * 256 - 1) / (4 * 256);
     if (blocks > (1LL << 30)) blocks = 1LL << 30;
     auto fn = (flags & 3u) == 3u ? k_copy_ref<true, true>

@@ -865,7 +865,7 @@ int mifft_copy_reference(const void* in, void* out, size_t bytes, unsigned flags
 {
     clear_error();
     if (!in || !out) return set_error(MIFFT_ERR_INVALID, "in / out must not be NULL");
-    if (flags & ~(unsigned)(MIFFT_COPY_NT_LOADS | MIFFT_COPY_NT_STORES))
+    if (flags & ~(unsigned)(MIFFT_COPY_NT_LOADS | MIFFT_COPY_NT_STORES | MIFFT_COPY_BLOCKED))
         return set_error(MIFFT_ERR_INVALID, "unknown flags 0x%x", flags);
     if ((uintptr_t)in % 16 || (uintptr_t)out % 16 || bytes % 16)
         return set_error(MIFFT_ERR_INVALID, "pointers and size must be multiples of 16 bytes");

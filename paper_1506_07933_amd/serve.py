@@ -226,6 +226,14 @@ def run_open_loop(schedule: Sequence[Request], core: SchedulerCore,
     return core.records
 
 
+def _pct(sorted_vals, p):
+    """The p-th percentile (nearest rank) of an ascending list."""
+    if not sorted_vals:
+        return math.nan
+    k = min(len(sorted_vals) - 1, max(0, int(math.ceil(p / 100.0 * len(sorted_vals))) - 1))
+    return sorted_vals[k]
+
+
 def summarize(records: Dict[int, Record], wall: float, bytes_per_req: Callable[[Record], float]):
     ok = [r for r in records.values() if r.status == "ok"]
     lat = sorted(r.latency for r in ok)
@@ -288,7 +296,11 @@ class GpuPoissonExecutor:
         # per-slot pinned staging of the generator's per-axis factors (a slot's
         # next request starts only after its previous one has completed)
         self.staging = [torch.empty(3 * 8 * nmax, dtype=torch.complex128, pin_memory=True) for _ in range(slots)]
-        self.events = [torch.cuda.Event() for _ in range(slots)]
+        # per slot: events around the solve itself (after the right-hand side
+        # is drawn), for the device time of each solve
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(slots)]
+        self.events0 = [torch.cuda.Event(enable_timing=True) for _ in range(slots)]
+        self.solve_ms: Dict[int, float] = {}
         self.outputs: Dict[int, object] = {}
         self.inputs: Dict[int, object] = {}
         self.keep_outputs = False
@@ -345,16 +357,19 @@ class GpuPoissonExecutor:
         s = self.streams[slot]
         f, u, ws = self._views(offset, req.n, req.prec)
         self._draw(f, req.rid, s, slot)
+        ev0 = self.events0[slot]
+        ev0.record(s)
         p.poisson(f, out=u, ws=ws, stream=s)
         ev = self.events[slot]
         ev.record(s)
-        return (req, ev, f, u, slot)
+        return (req, ev, f, u, slot, ev0)
 
     def poll(self, handle) -> bool:
         return handle[1].query()
 
     def release(self, handle) -> None:
-        req, ev, f, u, slot = handle
+        req, ev, f, u, slot, ev0 = handle
+        self.solve_ms[req.rid] = ev0.elapsed_time(ev)
         if self.keep_outputs:
             # copies for the caller (tests), finished before the pool range
             # is handed to the next request
@@ -443,6 +458,10 @@ def serve(n_requests: int = 2000, rate: float = 200.0, seed: int = 0, sizes=(64,
                     "mean_queue_depth": mean_queue_depth(core.depth_log),
                     "queued_requests": sum(1 for w in waited if w > 1e-3),
                     "max_admission_wait_ms": max(waited) * 1e3 if waited else math.nan,
+                    # device time of the solves alone (events around each solve, after its
+                    # right-hand side is drawn); p50_ms / p99_ms include the draw and any wait
+                    "p50_solve_ms": _pct(sorted(ex.solve_ms.values()), 50),
+                    "p99_solve_ms": _pct(sorted(ex.solve_ms.values()), 99),
                     "timeline_t_queue_inflight_bytes": timeline(core.depth_log)})
     return summary, recs, ex
 

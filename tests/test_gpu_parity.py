@@ -466,9 +466,11 @@ def test_pattern_copy_reference_kernel():
                                   es_in, es_out, gs_in, gs_out, 16, 8, 0, None) == 1
     assert lib.mifft_pattern_copy(0, a.data_ptr(), a.numel(), a.data_ptr(), a.numel(), L, cols, groups, es_in,
                                   es_out, gs_in, gs_out, 16, 8, 0, None) == 1
-    # the contiguous reference copy, every load / store flavour, ragged grid
+    # the contiguous reference copy, every load / store flavour, strided or
+    # in 8 KiB blocks (the size here is not a multiple of a block)
     c = torch.empty_like(a)
-    for flags in (0, 1, 2, 3):
+    assert (a.numel() * 8) % 8192 != 0
+    for flags in range(8):
         c.zero_()
         assert lib.mifft_copy_reference(a.data_ptr(), c.data_ptr(), a.numel() * 8, flags, 3, None) == 0
         np.testing.assert_array_equal(host(c), src)
