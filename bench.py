@@ -243,6 +243,11 @@ def workload_mode(args):
         bp = BatchPlan(shapes, "fp32")
         out["persistent_graph_ms"] = time_fn(lambda: bp.forward(xs, outs, graph=True), args.warmup, args.steps)
         assert not bp.aborted()
+        bt = BatchPlan(shapes, "fp32", tune=True)
+        out["persistent_tuned_graph_ms"] = time_fn(lambda: bt.forward(xs, outs, graph=True), args.warmup, args.steps)
+        assert not bt.aborted()
+        out["tuned_choices"] = [l for l in bt.describe().splitlines() if l.startswith("stage=")]
+        bt.close()
         bk = BatchPlan(shapes, "fp32", mode="kernels")
         out["per_pass_kernels_ms"] = time_fn(lambda: bk.forward(xs, outs), args.warmup, args.steps)
         bg = BatchPlan(shapes, "fp32", mode="grouped")
@@ -401,15 +406,20 @@ def secondary(torch, np, steps):
     bp = BatchPlan(shapes, "fp32")
     g = time_fn(lambda: bp.forward(xs, outs, graph=True), 2, steps)
     assert not bp.aborted()
+    bt = BatchPlan(shapes, "fp32", tune=True)
+    gt = time_fn(lambda: bt.forward(xs, outs, graph=True), 2, steps)
+    assert not bt.aborted()
     bk = BatchPlan(shapes, "fp32", mode="kernels")
     k = time_fn(lambda: bk.forward(xs, outs), 2, steps)
     bg = BatchPlan(shapes, "fp32", mode="grouped")
     gg = time_fn(lambda: bg.forward(xs, outs, graph=True), 2, steps)
-    out["batched_64_uneven_fp32"] = {"persistent_graph_ms": round(g, 4), "per_pass_kernels_ms": round(k, 4),
+    out["batched_64_uneven_fp32"] = {"persistent_graph_ms": round(g, 4), "persistent_tuned_graph_ms": round(gt, 4),
+                                     "per_pass_kernels_ms": round(k, 4),
                                      "grouped_graph_ms": round(gg, 4), "elements": nb,
                                      "persistent_alg_GBps": round(48 * nb / g / 1e6, 1),
                                      "grouped_alg_GBps": round(48 * nb / gg / 1e6, 1)}
     bp.close()
+    bt.close()
     bk.close()
     bg.close()
     del xs, outs

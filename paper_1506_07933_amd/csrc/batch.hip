@@ -48,6 +48,10 @@ struct mifft_batch_s {
     unsigned grid = 0;
     size_t lds = 0;
     std::map<int, void*> tw;
+    int dev = 0;
+    // per (stage, line length): code-path variant and queue item size (KiB);
+    // the defaults are variant 0 and 64 KiB (MIFFT_BATCH_ITEM_KIB overrides)
+    std::map<std::pair<int, int>, std::pair<int, int>> choice;
     // per-pass kernel path: one plan per distinct shape
     std::map<std::vector<int>, mifft_plan> plans;
     // graph replay
@@ -100,6 +104,266 @@ mifft_batch_s::~mifft_batch_s()
 
 namespace mifft {
 
+static int batch_enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t s);
+
+static void free_tables(mifft_batch_s* b)
+{
+    if (b->d_passes) hipFree(b->d_passes);
+    if (b->d_item_pass) hipFree(b->d_item_pass);
+    if (b->d_counters) hipFree(b->d_counters);
+    b->d_passes = nullptr;
+    b->d_item_pass = nullptr;
+    b->d_counters = nullptr;
+}
+
+// (Re)build the work queue of the persistent kernel from b->dims and the
+// per-(stage, length) choices, upload its tables and size the grid.
+static int build_queue(mifft_batch_s* b)
+{
+    const int count = b->count, prec = b->prec;
+    const int* dims = b->dims.data();
+    const size_t esz = prec == MIFFT_FP64 ? 16 : 8;
+    free_tables(b);
+    b->passes.clear();
+    for (int k = 0; k < kBatchStages; ++k) b->stage_items[k] = 0;
+    // ---- passes in queue order: all z, then all y, then all x
+    std::vector<BatchPass>& P = b->passes;
+    std::vector<int> last(count, -1); // index of each transform's latest pass
+    size_t max_lds = 0; // dynamic LDS elements of the largest pass
+    // data per queue item (MIFFT_BATCH_ITEM_KIB overrides the 64 KiB default)
+    size_t default_item = 64 * 1024;
+    if (const char* e = getenv("MIFFT_BATCH_ITEM_KIB")) {
+        const long v = atol(e);
+        if (v > 0 && v <= 64 * 1024) default_item = (size_t)v * 1024;
+    }
+    for (int stage = 0; stage < 3; ++stage) {
+        // Within a stage the passes are ordered by line length, so that the
+        // workgroups running at any moment mostly execute the same
+        // per-length code (one instruction-cache working set, not many).
+        std::vector<int> order(count);
+        for (int t = 0; t < count; ++t) order[t] = t;
+        auto len_of = [&](int t) { return dims[3 * t + (stage == 0 ? 2 : (stage == 1 ? 1 : 0))]; };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return len_of(a) < len_of(c); });
+        for (int t : order) {
+            const int n0 = dims[3 * t], n1 = dims[3 * t + 1], n2 = dims[3 * t + 2];
+            const int L = stage == 0 ? n2 : (stage == 1 ? n1 : n0);
+            if (L == 1) continue;
+            int var = 0;
+            size_t item_bytes = default_item;
+            auto ch = b->choice.find({stage, L});
+            if (ch != b->choice.end()) {
+                var = batch_var_distinct(L, ch->second.first) ? ch->second.first : 0;
+                item_bytes = (size_t)ch->second.second * 1024;
+            }
+            BatchPass p{};
+            p.kind = stage == 0 ? 0 : 1;
+            p.code = kBatchVariants * menu_code(L) + var;
+            p.L = L;
+            p.tpl = threads_per_line(L, batch_var_policy(var), batch_var_emul(var));
+            p.xform = t;
+            p.from_in = last[t] < 0 ? 1 : 0;
+            // z: lines per wavefront sub-tile; y / x: columns per workgroup tile
+            p.per_wave = stage == 0 ? 64 / p.tpl : batch_tile_cols(p.tpl);
+            if (stage == 0) {
+                p.units = (long long)n0 * n1;
+                p.subtiles = (int)((p.units + p.per_wave - 1) / p.per_wave);
+            } else if (stage == 1) {
+                p.cols = n2;
+                p.gs = (long long)n1 * n2;
+                p.es = n2;
+                p.subtiles_per_group = (p.cols + p.per_wave - 1) / p.per_wave;
+                p.subtiles = p.subtiles_per_group * n0;
+                p.units = (long long)n0 * n2;
+            } else {
+                p.cols = n1 * n2;
+                p.gs = 0;
+                p.es = (long long)n1 * n2;
+                p.subtiles_per_group = (p.cols + p.per_wave - 1) / p.per_wave;
+                p.subtiles = p.subtiles_per_group;
+                p.units = p.cols;
+            }
+            // queue items of ~item_bytes of data; z items are a multiple of the
+            // wavefronts per workgroup (one sub-tile run per wavefront)
+            const size_t sub_bytes = (size_t)p.per_wave * L * esz;
+            const int unit = stage == 0 ? kBatchWaves : 1;
+            int spi = (int)((item_bytes + sub_bytes * unit - 1) / (sub_bytes * unit)) * unit;
+            spi = std::max(unit, std::min(spi, ((p.subtiles + unit - 1) / unit) * unit));
+            p.sub_per_item = spi;
+            p.nitems = (p.subtiles + spi - 1) / spi;
+            p.stage = stage;
+            p.dep = last[t];
+            p.dep_target = last[t] >= 0 ? P[last[t]].nitems : 0;
+            p.dep_stage = last[t] >= 0 ? P[last[t]].stage : 0;
+            p.done = (int)P.size();
+            auto it = b->tw.find(L);
+            if (it == b->tw.end()) {
+                void* w = nullptr;
+                if (hipMalloc(&w, (size_t)L * esz) != hipSuccess) return set_error(MIFFT_ERR_NOMEM, "twiddles");
+                hipError_t e = prec == MIFFT_FP64 ? launch_twiddles<double>((cx<double>*)w, L, nullptr)
+                                                  : launch_twiddles<float>((cx<float>*)w, L, nullptr);
+                if (e != hipSuccess) {
+                    hipFree(w);
+                    return set_error(MIFFT_ERR_DEVICE, "twiddle kernel: %s", hipGetErrorString(e));
+                }
+                it = b->tw.emplace(L, w).first;
+            }
+            p.tw = it->second;
+            last[t] = (int)P.size();
+            P.push_back(p);
+            max_lds = std::max(max_lds, (size_t)batch_lds_elems(L, p.tpl, prec == MIFFT_FP32));
+        }
+    }
+    int start = 0;
+    for (BatchPass& p : P) {
+        p.item_start = start;
+        start += p.nitems;
+        b->stage_items[p.stage] += p.nitems;
+    }
+    b->total_items = start;
+    b->ncounters = (int)P.size() + 2 + kBatchStages;
+    b->lds = max_lds * esz;
+    std::vector<int> item_pass((size_t)b->total_items);
+    for (size_t k = 0; k < P.size(); ++k)
+        for (int it = 0; it < P[k].nitems; ++it) item_pass[(size_t)P[k].item_start + it] = (int)k;
+    if (hipMalloc(&b->d_item_pass, sizeof(int) * item_pass.size()) != hipSuccess ||
+        hipMemcpy(b->d_item_pass, item_pass.data(), sizeof(int) * item_pass.size(), hipMemcpyHostToDevice) !=
+            hipSuccess)
+        return set_error(MIFFT_ERR_NOMEM, "batch item table");
+    if (hipMalloc(&b->d_passes, sizeof(BatchPass) * P.size()) != hipSuccess ||
+        hipMalloc(&b->d_counters, sizeof(int) * b->ncounters) != hipSuccess)
+        return set_error(MIFFT_ERR_NOMEM, "batch tables");
+    if (hipMemcpy(b->d_passes, P.data(), sizeof(BatchPass) * P.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(b->d_counters, 0, sizeof(int) * b->ncounters) != hipSuccess)
+        return set_error(MIFFT_ERR_DEVICE, "uploading the batch tables");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->dev) != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "device properties");
+    const int per_cu = prec == MIFFT_FP64 ? mifft_batch_blocks_per_cu_double(b->lds)
+                                          : mifft_batch_blocks_per_cu_float(b->lds);
+    long long grid = (long long)prop.multiProcessorCount * per_cu;
+    if (grid > b->total_items) grid = b->total_items;
+    b->grid = (unsigned)std::max(1LL, grid);
+    return MIFFT_OK;
+}
+
+static const char* const kStageName[kBatchStages] = {"z", "y", "x"};
+
+// MIFFT_TUNE for the persistent kernel: per (stage, line length) of the
+// batch, the code-path variant (radix order, radix groups per thread) and
+// the queue item size, chosen by timing the whole batch (one persistent
+// launch; 2 untimed + 5 timed on scratch buffers of the batch's shapes) for
+// each candidate of one (stage, length) at a time while the others keep
+// their current choice, the largest (stage, length) by data first --
+// planning by measurement as in the MEASURE planner of Sec. 3.  Choices
+// stored in the wisdom table (MIFFT_WISDOM) are applied without timing.
+static int tune_batch(mifft_batch_s* b)
+{
+    const size_t esz = b->prec == MIFFT_FP64 ? 16 : 8;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->dev) != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "device properties");
+    char arch[16];
+    snprintf(arch, sizeof(arch), "%.*s", 6, prop.gcnArchName);
+    auto key = [&](int stage, int L) {
+        char k[96];
+        snprintf(k, sizeof(k), "%s|%s|batch_%s|L=%d", arch, b->prec == MIFFT_FP64 ? "fp64" : "fp32",
+                 kStageName[stage], L);
+        return std::string(k);
+    };
+    // (stage, length) groups and their data
+    std::map<std::pair<int, int>, double> data;
+    for (int t = 0; t < b->count; ++t) {
+        const int* d = &b->dims[3 * t];
+        const double bytes = (double)d[0] * d[1] * d[2] * esz;
+        for (int stage = 0; stage < 3; ++stage) {
+            const int L = d[stage == 0 ? 2 : (stage == 1 ? 1 : 0)];
+            if (L > 1) data[{stage, L}] += bytes;
+        }
+    }
+    std::vector<std::pair<int, int>> todo;
+    for (const auto& kv : data) {
+        int pol = 0, emul = 1, kib = 64;
+        if (wisdom_batch_get(key(kv.first.first, kv.first.second), &pol, &emul, &kib)) {
+            const int var = pol == 2 ? 1 : (emul == 2 ? 2 : 0);
+            b->choice[kv.first] = {var, kib};
+        } else {
+            todo.push_back(kv.first);
+        }
+    }
+    if (todo.empty()) return build_queue(b);
+    std::sort(todo.begin(), todo.end(), [&](const auto& a, const auto& c) { return data[a] > data[c]; });
+
+    // scratch inputs and outputs of the batch's shapes
+    std::vector<void*> in(b->count, nullptr), out(b->count, nullptr);
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = MIFFT_OK;
+    for (int t = 0; t < b->count && rc == MIFFT_OK; ++t) {
+        const size_t n = (size_t)b->dims[3 * t] * b->dims[3 * t + 1] * b->dims[3 * t + 2] * esz;
+        if (hipMalloc(&in[t], n) != hipSuccess || hipMalloc(&out[t], n) != hipSuccess ||
+            hipMemset(in[t], 0, n) != hipSuccess)
+            rc = set_error(MIFFT_ERR_NOMEM, "tuning scratch buffers");
+    }
+    if (rc == MIFFT_OK && (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+                           hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = set_error(MIFFT_ERR_DEVICE, "tuning stream / events");
+    // whole-batch time of the current choices, microseconds (< 0: failed)
+    auto measure = [&]() -> double {
+        if (build_queue(b)) return -1;
+        for (int w = 0; w < 2; ++w)
+            if (batch_enqueue(b, in.data(), out.data(), s)) return -1;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < 5; ++r)
+            if (batch_enqueue(b, in.data(), out.data(), s)) return -1;
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) return -1;
+        int flag = 0;
+        if (hipMemcpy(&flag, b->d_counters + 1 + b->passes.size(), sizeof(int), hipMemcpyDeviceToHost) !=
+                hipSuccess ||
+            flag)
+            return -1;
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        return ms * 1e3 / 5;
+    };
+    std::vector<std::pair<std::string, std::vector<double>>> stored;
+    for (const auto& g : todo) {
+        if (rc) break;
+        const int L = g.second;
+        std::pair<int, int> best{0, 64};
+        double best_us = 1e30;
+        for (int var = 0; var < kBatchVariants; ++var) {
+            if (!batch_var_distinct(L, var)) continue;
+            for (int kib : {32, 64, 128}) {
+                b->choice[g] = {var, kib};
+                const double us = measure();
+                if (us < 0) {
+                    rc = set_error(MIFFT_ERR_DEVICE, "tuning run failed (stage %s, L=%d, variant %d)",
+                                   kStageName[g.first], L, var);
+                    break;
+                }
+                if (us < best_us) {
+                    best_us = us;
+                    best = {var, kib};
+                }
+            }
+            if (rc) break;
+        }
+        b->choice[g] = best;
+        stored.push_back({key(g.first, L), {(double)batch_var_policy(best.first), (double)batch_var_emul(best.first),
+                                            (double)best.second, best_us}});
+    }
+    if (s) hipStreamSynchronize(s);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (s) hipStreamDestroy(s);
+    for (void* p : in)
+        if (p) hipFree(p);
+    for (void* p : out)
+        if (p) hipFree(p);
+    if (rc) return rc;
+    wisdom_batch_put(stored);
+    return build_queue(b);
+}
+
 int batch_create(mifft_batch* out, int count, const int* dims, int kind, int prec, unsigned flags)
 {
     if (!out || !dims) return set_error(MIFFT_ERR_INVALID, "out / dims is NULL");
@@ -111,10 +375,6 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
     if ((flags & MIFFT_BATCH_GROUPED) && (flags & MIFFT_BATCH_KERNELS))
         return set_error(MIFFT_ERR_INVALID, "MIFFT_BATCH_GROUPED and MIFFT_BATCH_KERNELS exclude each other");
     if (kind != MIFFT_C2C) return set_error(MIFFT_ERR_UNSUPPORTED, "batches are C2C only");
-    if ((flags & MIFFT_TUNE) && !(flags & (MIFFT_BATCH_KERNELS | MIFFT_BATCH_GROUPED)))
-        return set_error(MIFFT_ERR_UNSUPPORTED,
-                         "MIFFT_TUNE tunes the per-pass plans of MIFFT_BATCH_KERNELS / MIFFT_BATCH_GROUPED; "
-                         "the persistent kernel has one compiled code path per length");
     if (count > kBatchMax) return set_error(MIFFT_ERR_UNSUPPORTED, "at most %d transforms per batch", kBatchMax);
     const bool grouped = flags & MIFFT_BATCH_GROUPED;
     const bool kernels = (flags & MIFFT_BATCH_KERNELS) || grouped;
@@ -161,129 +421,16 @@ int batch_create(mifft_batch* out, int count, const int* dims, int kind, int pre
             b->plans[key] = p;
         }
     } else {
-        // ---- passes in queue order: all z, then all y, then all x
-        std::vector<BatchPass>& P = b->passes;
-        std::vector<int> last(count, -1); // index of each transform's latest pass
-        size_t max_lds = 0; // dynamic LDS elements of the largest pass
+        b->dev = dev;
         if (const char* e = getenv("MIFFT_BATCH_PUBLISH_EVERY")) {
             const int v = atoi(e);
             if (v > 0) b->publish_every = v;
         }
-        // data per queue item (MIFFT_BATCH_ITEM_KIB overrides the 64 KiB default)
-        size_t item_bytes = 64 * 1024;
-        if (const char* e = getenv("MIFFT_BATCH_ITEM_KIB")) {
-            const long v = atol(e);
-            if (v > 0 && v <= 64 * 1024) item_bytes = (size_t)v * 1024;
-        }
-        for (int stage = 0; stage < 3; ++stage) {
-            // Within a stage the passes are ordered by line length, so that the
-            // workgroups running at any moment mostly execute the same
-            // per-length code (one instruction-cache working set, not many).
-            std::vector<int> order(count);
-            for (int t = 0; t < count; ++t) order[t] = t;
-            auto len_of = [&](int t) { return dims[3 * t + (stage == 0 ? 2 : (stage == 1 ? 1 : 0))]; };
-            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return len_of(a) < len_of(b); });
-            for (int t : order) {
-                const int n0 = dims[3 * t], n1 = dims[3 * t + 1], n2 = dims[3 * t + 2];
-                const int L = stage == 0 ? n2 : (stage == 1 ? n1 : n0);
-                if (L == 1) continue;
-                BatchPass p{};
-                p.kind = stage == 0 ? 0 : 1;
-                p.code = menu_code(L);
-                p.L = L;
-                p.tpl = threads_per_line(L, 0, 1);
-                p.xform = t;
-                p.from_in = last[t] < 0 ? 1 : 0;
-                // z: lines per wavefront sub-tile; y / x: columns per workgroup tile
-                p.per_wave = stage == 0 ? 64 / p.tpl : batch_tile_cols(p.tpl);
-                if (stage == 0) {
-                    p.units = (long long)n0 * n1;
-                    p.subtiles = (int)((p.units + p.per_wave - 1) / p.per_wave);
-                } else if (stage == 1) {
-                    p.cols = n2;
-                    p.gs = (long long)n1 * n2;
-                    p.es = n2;
-                    p.subtiles_per_group = (p.cols + p.per_wave - 1) / p.per_wave;
-                    p.subtiles = p.subtiles_per_group * n0;
-                    p.units = (long long)n0 * n2;
-                } else {
-                    p.cols = n1 * n2;
-                    p.gs = 0;
-                    p.es = (long long)n1 * n2;
-                    p.subtiles_per_group = (p.cols + p.per_wave - 1) / p.per_wave;
-                    p.subtiles = p.subtiles_per_group;
-                    p.units = p.cols;
-                }
-                // queue items of ~item_bytes of data; z items are a multiple of the
-                // wavefronts per workgroup (one sub-tile run per wavefront)
-                const size_t sub_bytes = (size_t)p.per_wave * L * esz;
-                const int unit = stage == 0 ? kBatchWaves : 1;
-                int spi = (int)((item_bytes + sub_bytes * unit - 1) / (sub_bytes * unit)) * unit;
-                spi = std::max(unit, std::min(spi, ((p.subtiles + unit - 1) / unit) * unit));
-                p.sub_per_item = spi;
-                p.nitems = (p.subtiles + spi - 1) / spi;
-                p.stage = stage;
-                p.dep = last[t];
-                p.dep_target = last[t] >= 0 ? P[last[t]].nitems : 0;
-                p.dep_stage = last[t] >= 0 ? P[last[t]].stage : 0;
-                p.done = (int)P.size();
-                auto it = b->tw.find(L);
-                if (it == b->tw.end()) {
-                    void* w = nullptr;
-                    if (hipMalloc(&w, (size_t)L * esz) != hipSuccess) {
-                        delete b;
-                        return set_error(MIFFT_ERR_NOMEM, "twiddles");
-                    }
-                    hipError_t e = prec == MIFFT_FP64 ? launch_twiddles<double>((cx<double>*)w, L, nullptr)
-                                                      : launch_twiddles<float>((cx<float>*)w, L, nullptr);
-                    if (e != hipSuccess) {
-                        hipFree(w);
-                        delete b;
-                        return set_error(MIFFT_ERR_DEVICE, "twiddle kernel: %s", hipGetErrorString(e));
-                    }
-                    it = b->tw.emplace(L, w).first;
-                }
-                p.tw = it->second;
-                last[t] = (int)P.size();
-                P.push_back(p);
-                max_lds = std::max(max_lds, (size_t)batch_lds_elems(L, p.tpl, prec == MIFFT_FP32));
-            }
-        }
-        int start = 0;
-        for (BatchPass& p : P) {
-            p.item_start = start;
-            start += p.nitems;
-            b->stage_items[p.stage] += p.nitems;
-        }
-        b->total_items = start;
-        b->ncounters = (int)P.size() + 2 + kBatchStages;
-        b->lds = max_lds * esz;
-        std::vector<int> item_pass((size_t)b->total_items);
-        for (size_t k = 0; k < P.size(); ++k)
-            for (int it = 0; it < P[k].nitems; ++it) item_pass[(size_t)P[k].item_start + it] = (int)k;
-        if (hipMalloc(&b->d_item_pass, sizeof(int) * item_pass.size()) != hipSuccess ||
-            hipMemcpy(b->d_item_pass, item_pass.data(), sizeof(int) * item_pass.size(), hipMemcpyHostToDevice) !=
-                hipSuccess) {
+        int rc = (flags & MIFFT_TUNE) ? tune_batch(b) : build_queue(b);
+        if (rc) {
             delete b;
-            return set_error(MIFFT_ERR_NOMEM, "batch item table");
+            return rc;
         }
-        if (hipMalloc(&b->d_passes, sizeof(BatchPass) * P.size()) != hipSuccess ||
-            hipMalloc(&b->d_counters, sizeof(int) * b->ncounters) != hipSuccess) {
-            delete b;
-            return set_error(MIFFT_ERR_NOMEM, "batch tables");
-        }
-        if (hipMemcpy(b->d_passes, P.data(), sizeof(BatchPass) * P.size(), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemset(b->d_counters, 0, sizeof(int) * b->ncounters) != hipSuccess) {
-            delete b;
-            return set_error(MIFFT_ERR_DEVICE, "uploading the batch tables");
-        }
-        hipDeviceProp_t prop;
-        hipGetDeviceProperties(&prop, dev);
-        const int per_cu = prec == MIFFT_FP64 ? mifft_batch_blocks_per_cu_double(b->lds)
-                                              : mifft_batch_blocks_per_cu_float(b->lds);
-        long long grid = (long long)prop.multiProcessorCount * per_cu;
-        if (grid > b->total_items) grid = b->total_items;
-        b->grid = (unsigned)std::max(1LL, grid);
     }
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -354,7 +501,7 @@ static int enqueue_grouped(mifft_batch b, void* const* in, void* const* out, hip
     return MIFFT_OK;
 }
 
-static int enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t s)
+static int batch_enqueue(mifft_batch b, void* const* in, void* const* out, hipStream_t s)
 {
     if (b->grouped) return enqueue_grouped(b, in, out, s);
     if (b->kernels) {
@@ -412,7 +559,7 @@ int batch_execute(mifft_batch b, void* const* in, void* const* out, void* stream
             return set_error(MIFFT_ERR_INVALID, "transform %d: buffers must be 16-byte aligned", t);
     }
     hipStream_t s = (hipStream_t)stream;
-    if (!graph) return enqueue(b, in, out, s);
+    if (!graph) return batch_enqueue(b, in, out, s);
     const bool same = b->exec && std::equal(b->g_in.begin(), b->g_in.end(), in) &&
                       std::equal(b->g_out.begin(), b->g_out.end(), out);
     if (!same) {
@@ -424,7 +571,7 @@ int batch_execute(mifft_batch b, void* const* in, void* const* out, void* stream
             return set_error(MIFFT_ERR_DEVICE, "capture stream");
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "begin capture: %s", hipGetErrorString(e));
-        int rc = enqueue(b, in, out, b->cap_stream);
+        int rc = batch_enqueue(b, in, out, b->cap_stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap_stream, &g);
         if (rc) {
@@ -484,6 +631,17 @@ int batch_describe(mifft_batch b, char* buf, size_t len)
         snprintf(line, sizeof(line), "mode=persistent transforms=%d passes=%zu items=%d grid=%u block=%d lds=%zu\n",
                  b->count, b->passes.size(), b->total_items, b->grid, kBatchBlock, b->lds);
         s += line;
+        // one line per (stage, length): the code path and item size in use
+        std::map<std::pair<int, int>, const BatchPass*> seen;
+        for (const BatchPass& p : b->passes) seen.emplace(std::make_pair(p.stage, p.L), &p);
+        for (const auto& kv : seen) {
+            const BatchPass& p = *kv.second;
+            const int var = p.code % kBatchVariants;
+            snprintf(line, sizeof(line), "stage=%s L=%d variant=%d policy=%d emul=%d tpl=%d sub_per_item=%d%s\n",
+                     kStageName[p.stage], p.L, var, batch_var_policy(var), batch_var_emul(var), p.tpl,
+                     p.sub_per_item, b->choice.count(kv.first) ? " chosen" : "");
+            s += line;
+        }
     }
     snprintf(buf, len, "%s", s.c_str());
     return MIFFT_OK;

@@ -75,9 +75,30 @@ constexpr int kBatchPend = 16;      // passes in a workgroup's pending completio
     X(37, 135) X(38, 144) X(39, 150) X(40, 160) X(41, 162) X(42, 180) X(43, 192) X(44, 200)        \
     X(45, 216) X(46, 225) X(47, 240) X(48, 250) X(49, 256)
 
+// Code paths per length: variant 0 uses the radix order of policy 0 with
+// one radix group per thread, 1 the radix-4-first order (policy 2), 2 two
+// radix groups per thread.  A variant that would equal variant 0 for a
+// length is not compiled (its code runs variant 0); the autotuner picks one
+// per (stage, length).
+constexpr int kBatchVariants = 3;
+__host__ __device__ constexpr int batch_var_policy(int v) { return v == 1 ? 2 : 0; }
+__host__ __device__ constexpr int batch_var_emul(int v) { return v == 2 ? 2 : 1; }
+__host__ __device__ constexpr bool batch_var_distinct(int L, int v)
+{
+    if (v == 1) {
+        const Factors a = factorize(L, 0), b = factorize(L, 2);
+        if (a.n != b.n) return true;
+        for (int i = 0; i < a.n; ++i)
+            if (a.r[i] != b.r[i]) return true;
+        return false;
+    }
+    if (v == 2) return threads_per_line(L, 0, 2) != threads_per_line(L, 0, 1);
+    return v == 0;
+}
+
 struct BatchPass {
     int kind;     // 0: contiguous z-lines, 1: strided columns
-    int code;     // menu index of the line length
+    int code;     // kBatchVariants x menu index of the line length + variant
     int L;
     int tpl;      // threads per line
     int xform;    // transform index (pointer slot)
@@ -238,9 +259,9 @@ template <typename T, int KIND, int SLOTS, bool PF, bool TWL, bool WG = false> s
 // items read twiddles from global memory and do not prefetch (register and
 // LDS budget).
 template <typename T> constexpr bool batch_tw_in_lds() { return MIFFT_BATCH_TWL && sizeof(T) == 4; }
-template <typename T, int L> constexpr bool batch_prefetches()
+template <typename T, int L, int P, int E> constexpr bool batch_prefetches()
 {
-    using S = FirstStageShape<L, threads_per_line(L, 0, 1), FirstRadix<typename RL<L, 0>::type>::value>;
+    using S = FirstStageShape<L, threads_per_line(L, P, E), FirstRadix<typename RL<L, P>::type>::value>;
     return MIFFT_BATCH_PF && sizeof(T) == 4 && S::SLOTS * sizeof(cx<T>) <= 128;
 }
 
@@ -299,20 +320,21 @@ __device__ __forceinline__ PassU load_pass(const MIFFT_CONST BatchPass* p)
     return u;
 }
 
-// One code path per length, kept out of line so each gets its own register
-// allocation.  z: the wavefront's sub-tiles first + wave, first + wave + 4,
-// ...; y / x: the workgroup's column tiles first, first + 1, ...
-template <typename T, int L>
+// One code path per (length, radix policy, radix groups per thread), kept
+// out of line so each gets its own register allocation.  z: the wavefront's
+// sub-tiles first + wave, first + wave + 4, ...; y / x: the workgroup's
+// column tiles first, first + 1, ...
+template <typename T, int L, int P, int E>
 __device__ __noinline__ void batch_item(const BatchPass* pp, const cx<T>* src, cx<T>* dst, int first, int last,
                                         int wave, int lane, MIFFT_LDS typename vec2_of<T>::type* lds)
 {
     using V = cx<T>;
     typedef typename vec2_of<T>::type N2;
     typedef MIFFT_GLOBAL N2 GV;
-    constexpr int TPL = threads_per_line(L, 0, 1);
-    using RLt = typename RL<L, 0>::type;
+    constexpr int TPL = threads_per_line(L, P, E);
+    using RLt = typename RL<L, P>::type;
     constexpr int R0 = FirstRadix<RLt>::value;
-    constexpr bool PF = batch_prefetches<T, L>();
+    constexpr bool PF = batch_prefetches<T, L, P, E>();
     constexpr bool TWL = batch_tw_in_lds<T>();
     constexpr int SLOTS = PF ? FirstStageShape<L, TPL, R0>::SLOTS : 0;
     const PassU p = load_pass((const MIFFT_CONST BatchPass*)pp);
@@ -410,6 +432,17 @@ __device__ __noinline__ void batch_item(const BatchPass* pp, const cx<T>* src, c
     }
 }
 
+template <typename T, int L, int V>
+__device__ __forceinline__ void batch_item_var(const BatchPass* p, const cx<T>* src, cx<T>* dst, int first,
+                                               int last, int wave, int lane,
+                                               MIFFT_LDS typename vec2_of<T>::type* lds)
+{
+    if constexpr (batch_var_distinct(L, V))
+        batch_item<T, L, batch_var_policy(V), batch_var_emul(V)>(p, src, dst, first, last, wave, lane, lds);
+    else
+        batch_item<T, L, 0, 1>(p, src, dst, first, last, wave, lane, lds);
+}
+
 template <typename T>
 __device__ __forceinline__ void batch_dispatch(int code, const BatchPass* p, const cx<T>* src, cx<T>* dst,
                                                int first, int last, int wave, int lane,
@@ -417,8 +450,14 @@ __device__ __forceinline__ void batch_dispatch(int code, const BatchPass* p, con
 {
     switch (code) {
 #define MIFFT_BATCH_CASE(I, LEN)                                                                  \
-    case I:                                                                                       \
-        batch_item<T, LEN>(p, src, dst, first, last, wave, lane, lds);                           \
+    case kBatchVariants * I:                                                                      \
+        batch_item_var<T, LEN, 0>(p, src, dst, first, last, wave, lane, lds);                    \
+        break;                                                                                    \
+    case kBatchVariants * I + 1:                                                                  \
+        batch_item_var<T, LEN, 1>(p, src, dst, first, last, wave, lane, lds);                    \
+        break;                                                                                    \
+    case kBatchVariants * I + 2:                                                                  \
+        batch_item_var<T, LEN, 2>(p, src, dst, first, last, wave, lane, lds);                    \
         break;
         MIFFT_BATCH_MENU(MIFFT_BATCH_CASE)
 #undef MIFFT_BATCH_CASE

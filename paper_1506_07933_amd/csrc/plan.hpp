@@ -173,6 +173,9 @@ const Plan* plan_of(mifft_plan h);
 int get_twiddles(Plan& plan, int L, void** out);
 
 int build_plan(Plan& plan, unsigned flags);
+// wisdom entries of the batched executor (tune.hip): [policy, emul, item KiB, microseconds]
+bool wisdom_batch_get(const std::string& key, int* policy, int* emul, int* item_kib);
+void wisdom_batch_put(const std::vector<std::pair<std::string, std::vector<double>>>& entries);
 void rebuild_poisson(Plan& plan); // re-derive the Poisson pass list from fwd / inv
 void apply_chunking(Plan& plan);  // interleave z/y (x^-1/z^-1) over plane chunks
 int build_pencil(Plan& plan, unsigned flags);

@@ -48,6 +48,16 @@ static bool choice_shape_ok(const Choice& c)
     return (c.B == 0 && c.lpw >= 1 && c.lpw <= 32) || (c.lpw == 0 && pow2_in(c.B, 1, 64));
 }
 
+// Entries of the batched executor ("...|batch_z|L=..", "..._y", "..._x"):
+// policy 0 or 2, one or two radix groups per thread, B = the queue item
+// size in KiB (32, 64 or 128), lpw unused (0).
+static bool is_batch_key(const std::string& k) { return k.find("|batch_") != std::string::npos; }
+static bool batch_choice_ok(const Choice& c)
+{
+    return (c.policy == 0 || c.policy == 2) && (c.emul == 1 || c.emul == 2) &&
+           (c.B == 32 || c.B == 64 || c.B == 128) && c.lpw == 0;
+}
+
 // One entry per line:  "key": [policy, emul, B, lpw, microseconds],
 static void load_wisdom_locked()
 {
@@ -61,9 +71,10 @@ static void load_wisdom_locked()
         const size_t a = line.find('"'), b = line.find('"', a + 1), c = line.find('[', b);
         if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
         Choice ch;
+        const std::string key = line.substr(a + 1, b - a - 1);
         if (sscanf(line.c_str() + c, "[%d, %d, %d, %d, %lf]", &ch.policy, &ch.emul, &ch.B, &ch.lpw, &ch.us) == 5 &&
-            choice_shape_ok(ch))
-            g_wisdom[line.substr(a + 1, b - a - 1)] = ch;
+            (is_batch_key(key) ? batch_choice_ok(ch) : choice_shape_ok(ch)))
+            g_wisdom[key] = ch;
     }
 }
 
@@ -182,6 +193,31 @@ static bool apply_wisdom_locked(Plan& plan, const char* arch)
             all = all && done;
         }
     return all;
+}
+
+// Batched executor's choices in the same table (the batch tuner lives in
+// batch.hip): look one up, or store several and write the file back.
+bool wisdom_batch_get(const std::string& key, int* policy, int* emul, int* item_kib)
+{
+    std::lock_guard<std::mutex> g(g_wmu);
+    load_wisdom_locked();
+    auto it = g_wisdom.find(key);
+    if (it == g_wisdom.end() || !batch_choice_ok(it->second)) return false;
+    *policy = it->second.policy;
+    *emul = it->second.emul;
+    *item_kib = it->second.B;
+    return true;
+}
+
+void wisdom_batch_put(const std::vector<std::pair<std::string, std::vector<double>>>& entries)
+{
+    std::lock_guard<std::mutex> g(g_wmu);
+    load_wisdom_locked();
+    for (const auto& e : entries) {
+        const Choice c{(int)e.second[0], (int)e.second[1], (int)e.second[2], 0, e.second[3]};
+        if (batch_choice_ok(c)) g_wisdom[e.first] = c;
+    }
+    if (!entries.empty()) save_wisdom_locked();
 }
 
 int tune_plan(Plan& plan)

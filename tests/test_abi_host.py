@@ -194,8 +194,6 @@ def test_batch_argument_validation(L):
     assert L.mifft_batch_create(C.byref(h), 2, dims, 1, 0, 0) == 2      # R2C batches not offered
     assert L.mifft_batch_create(C.byref(h), 2, dims, 0, 0, 0x100) == 1  # unknown flag
     assert L.mifft_batch_create(C.byref(h), 2, dims, 0, 0, 4 | 8) == 1   # kernels and grouped
-    assert L.mifft_batch_create(C.byref(h), 2, dims, 0, 0, 1) == 2       # MIFFT_TUNE: not persistent
-    assert b"MIFFT_TUNE" in L.mifft_last_error()
     big = (C.c_int * 6)(512, 64, 64, 48, 48, 48)
     assert L.mifft_batch_create(C.byref(h), 2, big, 0, 0, 0) == 2       # 512 not in the menu
     assert L.mifft_batch_create(C.byref(h), 129, (C.c_int * 387)(*([8] * 387)), 0, 0, 0) == 2

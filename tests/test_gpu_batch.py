@@ -118,3 +118,50 @@ def test_batch_grouped_mode():
     (res_gg,) = run_batch(shapes, data, "fp32", mode="grouped", graph=True)
     for t in range(len(shapes)):
         np.testing.assert_array_equal(res_gg[t], res_g[t])
+
+
+def test_batch_tuned_persistent_launch(tmp_path):
+    """MIFFT_TUNE in the one persistent launch: per (stage, length) the tuner
+    picks a code path (radix order, radix groups per thread) and an item
+    size by timing the whole batch; the results keep parity with the oracle
+    and with the untuned launch, the choices land in the wisdom file, and a
+    second tuned batch of the same shapes reuses them."""
+    import json
+    import os
+    from paper_1506_07933_amd import BatchPlan
+    wisdom = tmp_path / "wisdom.json"
+    os.environ["MIFFT_WISDOM"] = str(wisdom)
+    try:
+        shapes, data = synth.batched_uneven(16, seed=7, dtype=np.complex64)
+        bp = BatchPlan(shapes, "fp32", tune=True)
+        desc = bp.describe()
+        print(desc, flush=True)
+        assert "chosen" in desc
+        xs = [torch.from_numpy(d).to(DEV) for d in data]
+        outs = [torch.empty_like(x) for x in xs]
+        bp.forward(xs, outs, graph=True)
+        torch.cuda.synchronize()
+        assert not bp.aborted()
+        (plain,) = run_batch(shapes, data, "fp32")
+        worst = 0.0
+        for s, d, o, r in zip(shapes, data, outs, plain):
+            got = o.cpu().numpy()
+            e = rel_l2(got, oracle.fft3d_c2c(d.astype(np.complex128), -1))
+            worst = max(worst, e)
+            assert e <= 5e-6, s
+            assert rel_l2(got, r) <= 5e-6, s
+        print("  tuned batch worst rel_l2 vs oracle %.3e" % worst, flush=True)
+        bp.close()
+        entries = json.loads(wisdom.read_text())
+        keys = [k for k in entries if "|batch_" in k]
+        lengths = {n for s in shapes for n in s if n > 1}
+        assert {k.split("|")[2] for k in keys} == {"batch_z", "batch_y", "batch_x"}
+        assert {int(k.split("L=")[1]) for k in keys} == lengths
+        for k in keys:
+            pol, emul, kib, lpw, us = entries[k]
+            assert pol in (0, 2) and emul in (1, 2) and kib in (32, 64, 128) and lpw == 0 and us > 0
+        again = BatchPlan(shapes, "fp32", tune=True)
+        assert again.describe() == desc        # the stored choices, applied without timing
+        again.close()
+    finally:
+        del os.environ["MIFFT_WISDOM"]
