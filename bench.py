@@ -228,8 +228,9 @@ def workload_mode(args):
     """One secondary workload alone (for rocprofv3): the 64 uneven transforms
     in one persistent graph launch and as per-pass kernels, 512^3 R2C
     Poisson solves (FP32 and FP64), one task's 512^3 slab share, the 4-D
-    512 x 256 x 128 x 64 C2C transform, the 512^3 spectral operators, or the
-    full served-Poisson replay."""
+    512 x 256 x 128 x 64 C2C transform, the 512^3 spectral operators, one
+    GPU's pencil share of a 1024^3 transform, the 256^3 R2C / C2R
+    transforms, or the full served-Poisson replay."""
     import numpy as np
     import torch
 
@@ -265,6 +266,27 @@ def workload_mode(args):
         out.update(pattern_mode(torch, time_fn, args.warmup, args.steps))
     elif args.mode == "oracle":
         out.update(cpu_baseline_configs(np))
+    elif args.mode == "pencil":
+        # one GPU's share of a 1024^3 C2C transform on a 4 x 4 grid: the fused
+        # z-FFT + pack and unpack + y-FFT kernels
+        from paper_1506_07933_amd import PencilPlan
+        pp = PencilPlan((1024, 1024, 1024), (4, 4), "fp32")
+        a = torch.from_numpy(synth.uniform_complex(pp.local_shape, np.complex64, seed=0)).cuda()
+        send = torch.empty(pp.send_shape, dtype=torch.complex64, device="cuda")
+        ob = torch.empty(pp.out_shape, dtype=torch.complex64, device="cuda")
+        out["pencil_share_fused_ms"] = time_fn(lambda: pp.forward_share(a, send, ob, fused=True), args.warmup,
+                                               args.steps)
+        pp.close()
+    elif args.mode == "r2c":
+        # 256^3 R2C forward and C2R inverse, FP32 and FP64
+        for prec, rd, cd in (("fp32", np.float32, torch.complex64), ("fp64", np.float64, torch.complex128)):
+            xr = torch.from_numpy(synth.normal_real((256, 256, 256), rd, seed=0)).cuda()
+            p = Plan((256, 256, 256), "r2c", prec)
+            Y = torch.empty((256, 256, 129), dtype=cd, device="cuda")
+            xo = torch.empty_like(xr)
+            out["r2c_256_%s_forward_ms" % prec] = time_fn(lambda: p.forward(xr, out=Y), args.warmup, args.steps)
+            out["r2c_256_%s_inverse_ms" % prec] = time_fn(lambda: p.inverse(Y, out=xo), args.warmup, args.steps)
+            p.close()
     elif args.mode == "serve":
         # the full served-Poisson replay: 2000 requests at 200 req/s (about 10 s)
         from paper_1506_07933_amd import serve
@@ -440,9 +462,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab", "nd", "spectral", "serve", "oracle",
-                                       "pattern"], default="fft",
+                                       "pattern", "pencil", "r2c"], default="fft",
                     help="copy: plain 1 GiB device copy (counter scaling); batched / poisson / "
-                         "slab / nd / spectral / serve: only that secondary workload (serve: the "
+                         "slab / nd / spectral / pencil / r2c / serve: only that secondary workload (serve: the "
                          "full 2000-request replay); oracle: the CPU oracle's times for those "
                          "workloads; pattern: copy rates of the strided passes' access pattern")
     args = ap.parse_args()
@@ -453,7 +475,7 @@ def main():
         sys.exit(2)
     if args.mode == "copy":
         return copy_mode(args)
-    if args.mode in ("batched", "poisson", "slab", "nd", "spectral", "serve", "oracle", "pattern"):
+    if args.mode in ("batched", "poisson", "slab", "nd", "spectral", "serve", "oracle", "pattern", "pencil", "r2c"):
         return workload_mode(args)
 
     import numpy as np

@@ -685,7 +685,25 @@ __global__ __launch_bounds__(1024) void k_c2r_z(RealArgs<T> a)
     c.out = reinterpret_cast<V*>(a.out) + lo * a.os_o + li * a.os_i;
     if (c.valid) {
         const V* in = reinterpret_cast<const V*>(a.in) + lo * a.is_o + li * a.is_i;
-        for (int k = c.t; k <= L; k += TPL) c.lds[lds_pad(k)] = in[k];
+        if constexpr (sizeof(T) == 4) {
+            // FP32: all loads of the line in flight before the first LDS store
+            // (512^3 Poisson solve 1.25 -> 1.20 ms; in FP64 this order made
+            // the 256^3 C2R slower, 0.18 -> 0.22 ms)
+            constexpr int NK = (L + 1 + TPL - 1) / TPL;
+            V v[NK];
+#pragma unroll
+            for (int i = 0; i < NK; ++i) {
+                const int k = c.t + i * TPL;
+                if (k <= L) v[i] = in[k];
+            }
+#pragma unroll
+            for (int i = 0; i < NK; ++i) {
+                const int k = c.t + i * TPL;
+                if (k <= L) c.lds[lds_pad(k)] = v[i];
+            }
+        } else {
+            for (int k = c.t; k <= L; k += TPL) c.lds[lds_pad(k)] = in[k];
+        }
     }
     c.sync();
     LineFFT<T, L, TPL, decltype(c), typename RL<L, P>::type>::run(c);

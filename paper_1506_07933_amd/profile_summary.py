@@ -34,7 +34,7 @@ def _csv(d: str, suffix: str):
     return rows
 
 
-def _fft_dispatches(rows, skip=("twiddles",)):
+def _fft_dispatches(rows, skip=("twiddles", "k_copy", "k_tile_copy")):
     """The transform's own dispatches (library kernels other than the twiddle
     generator), in launch order."""
     rows = [r for r in rows if "mifft::k_" in r["Kernel_Name"]
@@ -73,8 +73,101 @@ def stats_table(trace_dir: str, title: str, command: str, note: str = "") -> str
     return "\n".join(lines) + "\n"
 
 
+def kernels_table(trace_dir, fetch_dir, write_dir, copy_fetch, copy_write, alg, title, command, counter_command,
+                  note=""):
+    """Per-kernel table of one workload: mean duration (kernel trace), mean
+    FETCH_SIZE / WRITE_SIZE per dispatch scaled by the plain-copy factors, and
+    for kernels with a known algorithmic byte count per dispatch (`alg`:
+    name fragment -> bytes) the ratio counter / algorithmic and the
+    algorithmic rate.  Returns (markdown, {kernel: traffic entry})."""
+    trace = _csv(trace_dir, "kernel_trace.csv")
+    sf, sw, cf, cw = copy_scale(copy_fetch, copy_write)
+    fr = _csv(fetch_dir, "counter_collection.csv")
+    wr = _csv(write_dir, "counter_collection.csv")
+
+    def short(name):
+        return name.split("(")[0].replace("void ", "")
+
+    def by_kernel(rows, key):
+        d = {}
+        for r in rows:
+            if "mifft::k_" not in r["Kernel_Name"]:
+                continue
+            d.setdefault(short(r["Kernel_Name"]), []).append(key(r))
+        return d
+
+    dur = by_kernel(trace, lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    fk = by_kernel(fr, lambda r: float(r["Counter_Value"]))
+    wk = by_kernel(wr, lambda r: float(r["Counter_Value"]))
+    lines = ["# " + title, "", "Command (kernel trace):", "", "    " + command, "",
+             "Counters (separate runs, `--pmc FETCH_SIZE` then `--pmc WRITE_SIZE`):", "", "    " + counter_command, "",
+             "Scale: a plain 1 GiB device copy reads FETCH_SIZE = %.1f KiB and WRITE_SIZE = %.1f KiB, so FETCH_SIZE "
+             "is multiplied by %.4f and WRITE_SIZE by %.4f." % (cf, cw, sf, sw), ""]
+    if note:
+        lines += [note, ""]
+    lines += ["| kernel | dispatches | mean us | HBM bytes / dispatch (counters) | algorithmic bytes | counter / alg "
+              "| alg GB/s | of 8 TB/s |", "|---|---|---|---|---|---|---|---|"]
+    traffic = {}
+    for k in sorted(dur, key=lambda k: -sum(dur[k])):
+        mean = statistics.mean(dur[k])
+        hbm = None
+        if k in fk and k in wk:
+            hbm = (statistics.mean(fk[k]) * sf + statistics.mean(wk[k]) * sw) * 1024.0
+        a = next((v for frag, v in alg.items() if frag in k), None)
+        cells = ["`%s`" % k, str(len(dur[k])), "%.1f" % mean, "%.4g" % hbm if hbm else "-",
+                 "%.4g" % a if a else "-", "%.4f" % (hbm / a) if (hbm and a) else "-",
+                 "%.0f" % (a / (mean * 1e-6) / 1e9) if a else "-",
+                 "%.3f" % (a / (mean * 1e-6) / 1e9 / 8000.0) if a else "-"]
+        lines.append("| " + " | ".join(cells) + " |")
+        if hbm:
+            traffic[k] = {"fetch_kib": statistics.mean(fk[k]), "write_kib": statistics.mean(wk[k]),
+                          "hbm_bytes_per_launch": hbm, "alg_bytes_per_launch": a, "mean_us": mean}
+    return "\n".join(lines) + "\n", traffic
+
+
+def _update_traffic(path, traffic):
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.dirname(here))
+    from bench import csrc_hash
+    data = {}
+    if os.path.exists(path):
+        data = json.load(open(path))
+    if data.get("csrc_hash") != csrc_hash():
+        data = {"csrc_hash": csrc_hash(), "kernels": {}}
+    data["kernels"].update(traffic)
+    json.dump(data, open(path, "w"), indent=1)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    if len(sys.argv) > 1 and sys.argv[1] == "kernels":
+        ap.add_argument("cmd")
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--fetch", required=True)
+        ap.add_argument("--write", required=True)
+        ap.add_argument("--copy-fetch", required=True)
+        ap.add_argument("--copy-write", required=True)
+        ap.add_argument("--alg", action="append", default=[],
+                        help="kernel-name fragment=algorithmic bytes per dispatch (repeatable)")
+        ap.add_argument("--title", required=True)
+        ap.add_argument("--command", required=True)
+        ap.add_argument("--counter-command", required=True)
+        ap.add_argument("--note", default="")
+        ap.add_argument("--out", required=True)
+        ap.add_argument("--traffic-json", default="")
+        a = ap.parse_args()
+        alg = {}
+        for item in a.alg:
+            frag, v = item.rsplit("=", 1)
+            alg[frag] = float(v)
+        text, traffic = kernels_table(a.trace, a.fetch, a.write, a.copy_fetch, a.copy_write, alg, a.title, a.command,
+                                      a.counter_command, a.note)
+        with open(a.out, "w") as f:
+            f.write(text)
+        if a.traffic_json and traffic:
+            _update_traffic(a.traffic_json, traffic)
+        print(text)
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "stats":
         ap.add_argument("cmd")
         ap.add_argument("--trace", required=True)
