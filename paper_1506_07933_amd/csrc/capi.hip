@@ -789,10 +789,11 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
         int pf = strided && q.vidx >= 0 ? variant_prefetch(plan->prec, q.vidx) : 0;
         snprintf(line, sizeof(line),
                  "%s kind=%s axis=%c L=%d policy=%d tpl=%d sgn=%d lines=%lld lpw=%d B=%d cols=%d groups=%d "
-                 "es=%lld/%lld gs=%lld/%lld off=%lld/%lld grid=%u block=%u lds=%zu pf=%d tpg=%d tiles=%d nt=%d\n",
+                 "es=%lld/%lld gs=%lld/%lld off=%lld/%lld grid=%u block=%u lds=%zu pf=%d tpg=%d tiles=%d nt=%d "
+                 "nto=%d\n",
                  tag, kn[q.kind], "zyx-"[q.tag < 3 ? q.tag : 3], q.L, pol, tpl, q.sgn, q.nlines, q.lines_per_wg,
                  q.B, q.cols, q.groups, q.es_in, q.es_out, q.gs_in, q.gs_out, q.off_in, q.off_out, q.grid,
-                 q.block, q.shmem, pf, q.tpg, q.ntiles, q.nt_in);
+                 q.block, q.shmem, pf, q.tpg, q.ntiles, q.nt_in, q.nt_out);
         s += line;
     };
     if (plan->pencil) {

@@ -227,6 +227,7 @@ template <typename T, bool WAVE_LOCAL> struct C2RCtx {
     using V = cx<T>;
     static constexpr bool kSyncAfterFirstRead = true;
     V* __restrict__ out; // the n2 reals of the line, as n2/2 pairs
+    bool nt;             // streaming stores
     V* lds;
     const V* twd;               // twiddles of the half length M, staged in LDS
     const V* __restrict__ twd2; // exp(-2 pi i k / n2), k = 0 .. M
@@ -253,7 +254,11 @@ template <typename T, bool WAVE_LOCAL> struct C2RCtx {
     __device__ __forceinline__ void lds_put(int idx, V v) { lds[lds_pad(idx)] = v; }
     __device__ __forceinline__ void final_put(int idx, V v)
     {
-        if (valid) out[idx] = cconj(v);
+        if (!valid) return;
+        if (nt)
+            store_nt<T>(out + idx, cconj(v));
+        else
+            out[idx] = cconj(v);
     }
     __device__ __forceinline__ V tw(int e) const { return twd[e]; }
     __device__ __forceinline__ void sync() const
@@ -625,6 +630,7 @@ template <typename T> struct RealArgs {
     void* out;
     const cx<T>* tw;  // half-length twiddles
     const cx<T>* tw2; // exp(-2 pi i k / n2)
+    int nt_out;       // streaming stores of the outputs
     int nlines;
     int lines_per_wg;
     int ni;
@@ -660,7 +666,11 @@ __global__ __launch_bounds__(1024) void k_r2c_z(RealArgs<T> a)
         V zb = cconj(c.lds[lds_pad(k == 0 ? 0 : L - k)]);
         V s = cadd(za, zb);
         V p = cmul(a.tw2[k], csub(za, zb));
-        out[k] = V{half * (s.x + p.y), half * (s.y - p.x)};
+        const V r{half * (s.x + p.y), half * (s.y - p.x)};
+        if (a.nt_out)
+            store_nt<T>(out + k, r);
+        else
+            out[k] = r;
     }
 }
 
@@ -680,6 +690,7 @@ __global__ __launch_bounds__(1024) void k_c2r_z(RealArgs<T> a)
     c.lds = smem + ln * lds_padded_len(L + 1);
     c.twd = stage_twiddles<T>(a.tw, L, smem + a.lines_per_wg * lds_padded_len(L + 1));
     c.twd2 = a.tw2;
+    c.nt = a.nt_out != 0;
     c.t = tid - ln * TPL;
     c.M = L;
     c.out = reinterpret_cast<V*>(a.out) + lo * a.os_o + li * a.os_i;

@@ -442,6 +442,7 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.out = dst;
         a.tw = (const V*)p.tw;
         a.tw2 = (const V*)p.tw2;
+        a.nt_out = p.nt_out;
         a.nlines = (int)p.nlines;
         a.lines_per_wg = p.lines_per_wg;
         a.ni = p.ni;
@@ -606,6 +607,17 @@ static int make_real_z(Plan& plan, Pass& p, PassKind kind, long long nlines)
     rc = get_twiddles(plan, plan.n2, (void**)&p.tw2);
     if (rc) return rc;
     set_contig_geometry(p, plan.prec, variant_tpl(plan.prec, vidx), M, nlines, lds_padded_len(M + 1));
+    // Streaming (non-temporal) stores where the output will not be read from
+    // the caches anyway: an R2C spectrum larger than the 256 MB Infinity
+    // Cache (a smaller one is read right away by the y-pass, from the cache:
+    // 256^3 FP64 forward 0.181 ms cached, 0.200 streaming), and a C2R result
+    // of 128 MiB or more (the end of the chain: 256^3 FP64 inverse 0.180 ->
+    // 0.165 ms; FP32, 64 MiB, 0.103 -> 0.109 ms streaming; 512^3 Poisson
+    // solve FP32 1.20 -> 1.17 ms, FP64 2.33 -> 2.25 ms with both streaming).
+    {
+        const double out_bytes = kind == P_R2C ? (double)nlines * (M + 1) * plan.esz : (double)nlines * M * plan.esz;
+        p.nt_out = out_bytes > (kind == P_R2C ? 256.0 : 128.0) * 1024 * 1024 - 1 ? 1 : 0;
+    }
     // complex side: lines of M + 1; real side: lines of M pairs
     const long long cl = M + 1, rl = M;
     if (kind == P_R2C)

@@ -48,6 +48,7 @@ struct Pass {
     int B = 1, log2B = 0, cols = 0, ntiles = 0, groups = 0;
     int tpg = 0; // tiles per group; 0: tiles over the flattened (group, column) index
     int nt_in = 0; // strided: streaming loads (tiles read whole, aligned 128-byte lines)
+    int nt_out = 0; // R2C / C2R z-pass: streaming stores (set by make_real_z from the output size)
     long long gs_in = 0, gs_out = 0, es_in = 0, es_out = 0;
     // pack / split
     FastDiv fd{1, 1ull << 32};
