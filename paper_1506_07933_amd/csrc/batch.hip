@@ -222,6 +222,8 @@ static int build_queue(mifft_batch_s* b)
     b->total_items = start;
     b->ncounters = (int)P.size() + 2 + kBatchStages;
     b->lds = max_lds * esz;
+    if (b->lds > 160 * 1024)
+        return set_error(MIFFT_ERR_UNSUPPORTED, "the chosen code paths need %zu bytes of LDS per workgroup", b->lds);
     std::vector<int> item_pass((size_t)b->total_items);
     for (size_t k = 0; k < P.size(); ++k)
         for (int it = 0; it < P[k].nitems; ++it) item_pass[(size_t)P[k].item_start + it] = (int)k;
@@ -305,9 +307,10 @@ static int tune_batch(mifft_batch_s* b)
     if (rc == MIFFT_OK && (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
                            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = set_error(MIFFT_ERR_DEVICE, "tuning stream / events");
-    // whole-batch time of the current choices, microseconds (< 0: failed)
+    // whole-batch time of the current choices, microseconds (-1: failed;
+    // -2: the choices do not fit the LDS of a workgroup, not a candidate)
     auto measure = [&]() -> double {
-        if (build_queue(b)) return -1;
+        if (const int e = build_queue(b)) return e == MIFFT_ERR_UNSUPPORTED ? -2 : -1;
         for (int w = 0; w < 2; ++w)
             if (batch_enqueue(b, in.data(), out.data(), s)) return -1;
         hipEventRecord(e0, s);
@@ -335,6 +338,7 @@ static int tune_batch(mifft_batch_s* b)
             for (int kib : {32, 64, 128}) {
                 b->choice[g] = {var, kib};
                 const double us = measure();
+                if (us == -2) continue;
                 if (us < 0) {
                     rc = set_error(MIFFT_ERR_DEVICE, "tuning run failed (stage %s, L=%d, variant %d)",
                                    kStageName[g.first], L, var);

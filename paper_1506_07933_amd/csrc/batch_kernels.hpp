@@ -31,7 +31,7 @@
 // synchronising only within the wavefront.  A y- or x-item is a run of
 // column tiles that the whole workgroup transforms one after another: a
 // tile is as many adjacent columns as the workgroup holds lines of that
-// length (256 / threads per line), so each row of a tile is one contiguous
+// length (kBatchBlock / threads per line), so each row of a tile is one contiguous
 // run of 64 bytes or more (narrow per-wavefront column tiles made the
 // strided passes several times slower).  Lanes left over when the threads
 // per line do not divide the wavefront or workgroup work on a private dummy
@@ -45,7 +45,10 @@
 namespace mifft {
 
 constexpr int kBatchMax = 128;      // transforms per batch (pointer slots in the kernel args)
-constexpr int kBatchBlock = 256;    // threads per workgroup (4 wavefronts)
+// threads per workgroup (8 wavefronts).  Measured on the 64-transform batch
+// (untuned): 256 threads 1.27 ms, 512 threads 1.09 ms, 1024 threads 1.19 ms
+// -- wider column tiles (512 / threads per line columns) read longer rows.
+constexpr int kBatchBlock = 512;
 constexpr int kBatchWaves = kBatchBlock / 64;
 constexpr int kBatchStages = 3;     // z, y, x
 constexpr int kBatchPend = 16;      // passes in a workgroup's pending completion list
