@@ -50,12 +50,12 @@ static bool choice_shape_ok(const Choice& c)
 
 // Entries of the batched executor ("...|batch_z|L=..", "..._y", "..._x"):
 // policy 0 or 2, one or two radix groups per thread, B = the queue item
-// size in KiB (32, 64 or 128), lpw unused (0).
+// size in KiB (32, 64, 128 or 256), lpw unused (0).
 static bool is_batch_key(const std::string& k) { return k.find("|batch_") != std::string::npos; }
 static bool batch_choice_ok(const Choice& c)
 {
     return (c.policy == 0 || c.policy == 2) && (c.emul == 1 || c.emul == 2) &&
-           (c.B == 32 || c.B == 64 || c.B == 128) && c.lpw == 0;
+           (c.B == 32 || c.B == 64 || c.B == 128 || c.B == 256) && c.lpw == 0;
 }
 
 // One entry per line:  "key": [policy, emul, B, lpw, microseconds],

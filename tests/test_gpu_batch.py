@@ -159,7 +159,7 @@ def test_batch_tuned_persistent_launch(tmp_path):
         assert {int(k.split("L=")[1]) for k in keys} == lengths
         for k in keys:
             pol, emul, kib, lpw, us = entries[k]
-            assert pol in (0, 2) and emul in (1, 2) and kib in (32, 64, 128) and lpw == 0 and us > 0
+            assert pol in (0, 2) and emul in (1, 2) and kib in (32, 64, 128, 256) and lpw == 0 and us > 0
         again = BatchPlan(shapes, "fp32", tune=True)
         assert again.describe() == desc        # the stored choices, applied without timing
         again.close()
