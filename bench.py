@@ -445,10 +445,11 @@ def secondary(torch, np, steps):
     bk.close()
     bg.close()
     del xs, outs
-    # served Poisson solves: a short open-loop replay, then the same replay
-    # under a budget small enough that admission has to queue requests
-    for key, budget in (("served_poisson", 32.0), ("served_poisson_budget_5GB", 5.0)):
-        s, recs, ex = serve.serve(n_requests=300, rate=200.0, seed=0, slots=4, budget_gb=budget)
+    # served Poisson solves: the configured open-loop replay (2000 requests at
+    # 200 req/s, about 10 s), then 300 of them under a budget small enough
+    # that admission has to queue requests
+    for key, nreq, budget in (("served_poisson", 2000, 32.0), ("served_poisson_budget_5GB", 300, 5.0)):
+        s, recs, ex = serve.serve(n_requests=nreq, rate=200.0, seed=0, slots=4, budget_gb=budget)
         ex.close()
         out[key] = {k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in s.items()}
     return out
