@@ -490,7 +490,7 @@ def main():
     x = torch.from_numpy(x_host).to("cuda:0")
     y = torch.empty_like(x)
     plan = Plan((N0, N1, N2), "c2c", "fp32")
-    passes = [l for l in plan.describe().splitlines() if l.startswith("forward")]
+    passes = [l for l in plan.describe().splitlines() if l.startswith("forward ")]
     axes = [l.split("axis=")[1][0] for l in passes]
 
     for _ in range(args.warmup):

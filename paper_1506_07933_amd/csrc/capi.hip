@@ -409,12 +409,23 @@ static int check_exec(mifft_plan plan, const void* in, void* out, void* ws, bool
     return MIFFT_OK;
 }
 
+// The pass list of a call: plans with the blocked schedule run their
+// transposed-schedule lists when the call is in place (in == out).
+static const std::vector<Pass>& fwd_list(const Plan& p, const void* in, const void* out)
+{
+    return (in == out && !p.fwd_ip.empty()) ? p.fwd_ip : p.fwd;
+}
+static const std::vector<Pass>& inv_list(const Plan& p, const void* in, const void* out)
+{
+    return (in == out && !p.inv_ip.empty()) ? p.inv_ip : p.inv;
+}
+
 int mifft_execute_forward_ws(mifft_plan plan, const void* in, void* out, void* ws, void* stream)
 {
     clear_error();
     int rc = check_exec(plan, in, out, ws, true);
     if (rc) return rc;
-    return run_passes(*plan, plan->fwd, in, out, ws, nullptr, nullptr, (hipStream_t)stream);
+    return run_passes(*plan, fwd_list(*plan, in, out), in, out, ws, nullptr, nullptr, (hipStream_t)stream);
 }
 
 int mifft_execute_inverse_ws(mifft_plan plan, const void* in, void* out, void* ws, void* stream)
@@ -422,7 +433,7 @@ int mifft_execute_inverse_ws(mifft_plan plan, const void* in, void* out, void* w
     clear_error();
     int rc = check_exec(plan, in, out, ws, true);
     if (rc) return rc;
-    return run_passes(*plan, plan->inv, in, out, ws, nullptr, nullptr, (hipStream_t)stream);
+    return run_passes(*plan, inv_list(*plan, in, out), in, out, ws, nullptr, nullptr, (hipStream_t)stream);
 }
 
 int mifft_execute_forward(mifft_plan plan, const void* in, void* out, void* stream)
@@ -430,7 +441,7 @@ int mifft_execute_forward(mifft_plan plan, const void* in, void* out, void* stre
     clear_error();
     int rc = check_exec(plan, in, out, nullptr, false);
     if (rc) return rc;
-    return run_passes(*plan, plan->fwd, in, out, plan->ws, nullptr, nullptr, (hipStream_t)stream);
+    return run_passes(*plan, fwd_list(*plan, in, out), in, out, plan->ws, nullptr, nullptr, (hipStream_t)stream);
 }
 
 int mifft_execute_inverse(mifft_plan plan, const void* in, void* out, void* stream)
@@ -438,7 +449,7 @@ int mifft_execute_inverse(mifft_plan plan, const void* in, void* out, void* stre
     clear_error();
     int rc = check_exec(plan, in, out, nullptr, false);
     if (rc) return rc;
-    return run_passes(*plan, plan->inv, in, out, plan->ws, nullptr, nullptr, (hipStream_t)stream);
+    return run_passes(*plan, inv_list(*plan, in, out), in, out, plan->ws, nullptr, nullptr, (hipStream_t)stream);
 }
 
 // Forward transform whose workspace is the file-scope device array below
@@ -493,7 +504,7 @@ int mifft_execute_forward_static(mifft_plan plan, const void* in, void* out, voi
                          dev);
     void* ws = nullptr;
     if (plan->ws_bytes && (rc = scratch_address(dev, &ws))) return rc;
-    return run_passes(*plan, plan->fwd, in, out, ws, nullptr, nullptr, (hipStream_t)stream);
+    return run_passes(*plan, fwd_list(*plan, in, out), in, out, ws, nullptr, nullptr, (hipStream_t)stream);
 }
 
 static int check_spectral(mifft_plan plan, const void* ws)
@@ -729,6 +740,7 @@ int mifft_profile_begin(mifft_plan plan, int max_calls)
     if (!is_live(plan)) return set_error(MIFFT_ERR_BADPLAN, "handle is not a live plan");
     if (max_calls < 1 || max_calls > 100000) return set_error(MIFFT_ERR_INVALID, "max_calls out of range");
     size_t longest = std::max(plan->fwd.size(), std::max(plan->inv.size(), plan->poisson.size()));
+    longest = std::max(longest, std::max(plan->fwd_ip.size(), plan->inv_ip.size()));
     if (longest < 4) longest = 4; // stage calls of pencil and slab plans
     const int stride = (int)longest + 1;
     const size_t need = (size_t)max_calls * stride;
@@ -781,7 +793,7 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
                                "strided_pack"};
     std::string s;
     auto add = [&](const char* tag, const Pass& q) {
-        char line[480];
+        char line[640];
         int pol = q.vidx >= 0 ? variant_policy(plan->prec, q.vidx) : -1;
         int tpl = q.vidx >= 0 ? variant_tpl(plan->prec, q.vidx) : 0;
         const bool strided = q.kind == mifft::P_STRIDED || q.kind == mifft::P_STRIDED_SPLIT ||
@@ -790,10 +802,12 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
         snprintf(line, sizeof(line),
                  "%s kind=%s axis=%c L=%d policy=%d tpl=%d sgn=%d lines=%lld lpw=%d B=%d cols=%d groups=%d "
                  "es=%lld/%lld gs=%lld/%lld off=%lld/%lld grid=%u block=%u lds=%zu pf=%d tpg=%d tiles=%d nt=%d "
-                 "nto=%d\n",
+                 "nto=%d gdiv=%d/%d gs2=%lld/%lld pm=%u/%lld ni=%d is=%lld/%lld os=%lld/%lld\n",
                  tag, kn[q.kind], "zyx-"[q.tag < 3 ? q.tag : 3], q.L, pol, tpl, q.sgn, q.nlines, q.lines_per_wg,
                  q.B, q.cols, q.groups, q.es_in, q.es_out, q.gs_in, q.gs_out, q.off_in, q.off_out, q.grid,
-                 q.block, q.shmem, pf, q.tpg, q.ntiles, q.nt_in, q.nt_out);
+                 q.block, q.shmem, pf, q.tpg, q.ntiles, q.nt_in, q.nt_out, q.gdiv_in, q.gdiv_out, q.gs2_in,
+                 q.gs2_out, q.kind == mifft::P_CONTIG_PACK ? q.fd.d : 0u, q.kind == mifft::P_CONTIG_PACK ? q.blk : 0,
+                 q.ni, q.is_o, q.is_i, q.os_o, q.os_i);
         s += line;
     };
     if (plan->pencil) {
@@ -818,6 +832,8 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
         for (const Pass& q : plan->fwd) add("forward", q);
         for (const Pass& q : plan->inv) add("inverse", q);
         for (const Pass& q : plan->poisson) add("poisson", q);
+        for (const Pass& q : plan->fwd_ip) add("forward_inplace", q);
+        for (const Pass& q : plan->inv_ip) add("inverse_inplace", q);
     }
     snprintf(buf, len, "%s", s.c_str());
     return MIFFT_OK;

@@ -89,7 +89,11 @@ template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
         v.y *= sgn;
         if constexpr (OUT_PACK) {
             uint32_t q = fdiv((uint32_t)idx, pm);
-            out[(long long)q * pblk + (idx - (int)(q * pm.d))] = v;
+            V* p = out + ((long long)q * pblk + (idx - (int)(q * pm.d)));
+            if constexpr (MIFFT_CONTIG_NT)
+                store_nt<T>(p, v);
+            else
+                *p = v;
         } else if constexpr (MIFFT_CONTIG_NT) {
             store_nt<T>(out + idx, v);
         } else {
@@ -345,10 +349,7 @@ __global__ __launch_bounds__(1024) void k_contig(ContigArgs<T> a)
     }
     const long long lo = line / a.ni, li = line - lo * a.ni;
     c.in = ain + lo * a.is_o + li * a.is_i;
-    if constexpr (OUT_PACK)
-        c.out = aout + line * (long long)a.pm.d;
-    else
-        c.out = aout + lo * a.os_o + li * a.os_i;
+    c.out = aout + lo * a.os_o + li * a.os_i; // with OUT_PACK: the line's place in block 0
     c.lds = smem + ln * lds_padded_len(L);
     c.twd = stage_twiddles<T>(a.tw, L, smem + a.lines_per_wg * lds_padded_len(L));
     c.t = tid - ln * TPL;
@@ -375,6 +376,11 @@ template <typename T> struct StridedArgs {
     FastDiv split;
     long long s_hi;
     int nt_in; // streaming loads (the planner's choice: whole, aligned input lines)
+    // Two-level group maps: with gdiv > 1 group g sits at
+    // (g / gdiv) * gs + (g % gdiv) * gs2 on that side (a blocked layout whose
+    // two block indices have unrelated strides), else at g * gs.
+    int gdiv_in, gdiv_out;
+    long long gs2_in, gs2_out;
 };
 
 // Whether the strided kernel of (T, L, policy, TPL) prefetches the next
@@ -433,8 +439,15 @@ __global__ __launch_bounds__(1024) void k_strided(StridedArgs<T> a)
             g = f / (unsigned)a.cols;
             col = f - g * (unsigned)a.cols;
         }
-        in_off = (long long)g * a.gs_in + col;
-        out_off = (long long)g * a.gs_out + col;
+        auto goff = [](unsigned gg, int d, long long s1, long long s2) -> long long {
+            if (d > 1) {
+                const unsigned q = gg / (unsigned)d;
+                return (long long)q * s1 + (long long)(gg - q * (unsigned)d) * s2;
+            }
+            return (long long)gg * s1;
+        };
+        in_off = goff(g, a.gdiv_in, a.gs_in, a.gs2_in) + col;
+        out_off = goff(g, a.gdiv_out, a.gs_out, a.gs2_out) + col;
         return g < (unsigned)a.groups;
     };
     const V* ain = a.in;

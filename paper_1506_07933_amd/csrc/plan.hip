@@ -298,7 +298,8 @@ void tile_pass(const Plan& plan, Pass& p)
     // -> 0.278 ms with streaming loads, the C2C 512^3 y-pass 0.415 -> 0.411).
     {
         const long long a = 128 / (long long)plan.esz;
-        bool ok = p.cols % p.B == 0 && p.es_in % a == 0 && (p.groups == 1 || p.gs_in % a == 0);
+        bool ok = p.cols % p.B == 0 && p.es_in % a == 0 && (p.groups == 1 || p.gs_in % a == 0) &&
+                  (p.gdiv_in <= 1 || p.gs2_in % a == 0);
         if (p.kind == P_STRIDED_SPLIT) ok = ok && p.blk % a == 0;
         p.nt_in = ok ? 1 : 0;
     }
@@ -310,7 +311,7 @@ void tile_pass(const Plan& plan, Pass& p)
 
 void tile_passes(Plan& plan)
 {
-    for (auto* list : {&plan.fwd, &plan.inv, &plan.poisson})
+    for (auto* list : {&plan.fwd, &plan.inv, &plan.poisson, &plan.fwd_ip, &plan.inv_ip})
         for (Pass& p : *list) tile_pass(plan, p);
     for (Pass* p : {&plan.py, &plan.py_split, &plan.sy, &plan.sy_pack, &plan.sx, &plan.sxi, &plan.syi,
                     &plan.syi_unpack})
@@ -404,6 +405,10 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.split = p.fd;
         a.s_hi = p.blk;
         a.nt_in = p.nt_in;
+        a.gdiv_in = p.gdiv_in;
+        a.gdiv_out = p.gdiv_out;
+        a.gs2_in = p.gs2_in;
+        a.gs2_out = p.gs2_out;
         auto fn = p.kind == P_STRIDED         ? v.strided
                   : p.kind == P_STRIDED_SPLIT ? v.strided_split
                                               : v.strided_osplit;
@@ -729,6 +734,91 @@ void apply_chunking(Plan& plan)
     plan.chunks = (plan.n0 + C - 1) / C;
 }
 
+// Variant of an L-point strided pass whose column tile is exactly B columns
+// wide (within 1024 threads and 136 KiB of LDS), the one with the most
+// threads per line; -1 if none.
+static int strided_variant_for_B(const Plan& plan, int L, int B)
+{
+    int best = -1;
+    for (int i = 0; i < variant_count(plan.prec); ++i) {
+        if (variant_L(plan.prec, i) != L || variant_policy(plan.prec, i) != 0) continue;
+        const int tpl = variant_tpl(plan.prec, i);
+        if ((long long)tpl * B > 1024 || (size_t)(B + 1) * L * plan.esz > 136 * 1024) continue;
+        if (best < 0 || tpl > variant_tpl(plan.prec, best)) best = i;
+    }
+    return best;
+}
+
+// Blocked schedule of an out-of-place C2C transform with the transposed
+// intermediate.  A column tile reads its rows from one contiguous block
+// when the pass before it stored them there, so each strided pass has one
+// contiguous side instead of none (a copy with the y / x tile pattern of
+// 512^3 ran at 5.3-5.4 TB/s with both sides strided, 5.7-5.8 TB/s with the
+// reads contiguous).  With W the tile width (256-byte rows), z = zb W + zc
+// and nb = n2 / W blocks:
+//   z:  X[x][y][z]             -> T[x][zb][y][zc]  (stores through the pack map, M = W)
+//   y:  tile (x, zb) of T      -> U[k1][zb][x][zc] (rows k1 n0 n2 apart)
+//   x:  tile (k1, zb) of U     -> X[k0][k1][k2]    (rows k0 n1 n2 apart)
+// Buffers: z IN -> OUT, y OUT -> WS, x WS -> OUT; the inverse runs the same
+// three passes conjugated (the axes of a 3-D DFT may be transformed in any
+// order).  In place (in == out) the z-pass would overwrite lines that are
+// not read yet, so those calls run the transposed-schedule lists, kept in
+// fwd_ip / inv_ip.  Returns whether the schedule applies.
+static bool build_blocked(Plan& plan, int vz)
+{
+    const int n0 = plan.n0, n1 = plan.n1, n2 = plan.n2;
+    const int W = (int)(256 / plan.esz);
+    if (plan.kind != MIFFT_C2C || vz < 0 || n0 < 2 || n1 < 2 || n2 % W != 0) return false;
+    if (const char* e = getenv("MIFFT_BLOCKED")) // "0": the transposed schedule (for comparison)
+        if (atoi(e) == 0) return false;
+    const int vy = strided_variant_for_B(plan, n1, W), vx = strided_variant_for_B(plan, n0, W);
+    if (vy < 0 || vx < 0) return false;
+    const int nb = n2 / W;
+    const long long N = (long long)n0 * n1 * n2;
+    if ((long long)nb * n0 >= (1LL << 31) || (long long)nb * n1 >= (1LL << 31) || N >= (1LL << 40)) return false;
+    std::vector<Pass> lists[2];
+    for (int d = 0; d < 2; ++d) {
+        const int sgn = d == 0 ? +1 : -1;
+        Pass z, y, x;
+        if (make_contig(plan, z, n2, (long long)n0 * n1, vz)) return false;
+        z.kind = P_CONTIG_PACK;
+        z.fd = make_fastdiv((uint32_t)W);
+        z.blk = (long long)n1 * W;
+        set_line_map(z, n1, (long long)n1 * n2, n2, (long long)n1 * n2, W);
+        z.sgn = sgn;
+        z.tag = 0;
+        z.src = B_IN;
+        z.dst = B_OUT;
+        // group g = x nb + zb: T block g at g n1 W; U row k1 at k1 n0 n2 + zb n0 W + x W
+        if (make_strided(plan, y, n1, W, n0 * nb, W, (long long)n1 * W, vy, W) || y.B != W) return false;
+        y.es_out = (long long)n0 * n2;
+        y.gs_out = W;
+        y.gs2_out = (long long)n0 * W;
+        y.gdiv_out = nb;
+        y.fixedB = W;
+        y.sgn = sgn;
+        y.tag = 1;
+        y.src = B_OUT;
+        y.dst = B_WS;
+        // group g = k1 nb + zb: U block g at g n0 W; X row k0 at k0 n1 n2 + g W
+        if (make_strided(plan, x, n0, W, n1 * nb, W, (long long)n0 * W, vx, W) || x.B != W) return false;
+        x.es_out = (long long)n1 * n2;
+        x.gs_out = W;
+        x.fixedB = W;
+        x.sgn = sgn;
+        x.tag = 2;
+        x.src = B_WS;
+        x.dst = B_OUT;
+        lists[d] = {z, y, x};
+    }
+    plan.fwd_ip = plan.fwd;
+    plan.inv_ip = plan.inv;
+    plan.fwd = lists[0];
+    plan.inv = lists[1];
+    plan.blocked = W;
+    return true;
+}
+
 int build_plan(Plan& plan, unsigned /*flags*/)
 {
     const bool real = plan.kind == MIFFT_R2C;
@@ -915,7 +1005,13 @@ int build_plan(Plan& plan, unsigned /*flags*/)
             v.back().dst = B_OUT;
         }
     }
-    if (T && has_z) apply_chunking(plan);
+    plan.fwd_ip.clear();
+    plan.inv_ip.clear();
+    plan.blocked = 0;
+    const char* chunk_env = getenv("MIFFT_CHUNK_MIB");
+    const bool chunked = chunk_env && atol(chunk_env) > 0;
+    if (T && has_z && !chunked) build_blocked(plan, vz);
+    if (T && has_z && !plan.blocked) apply_chunking(plan);
     bool inv_uses_ws = false, fwd_uses_ws = false;
     for (const Pass& q : plan.inv) inv_uses_ws |= (q.src == B_WS || q.dst == B_WS);
     for (const Pass& q : plan.fwd) fwd_uses_ws |= (q.src == B_WS || q.dst == B_WS);
@@ -953,7 +1049,7 @@ Extent pass_extent(const Pass& p, size_t esz)
     case P_CONTIG_PACK: {
         const long long M = p.fd.d;
         e.in = oi + line_map_extent(p.ni, p.nlines, p.is_o, p.is_i, p.L);
-        e.out = oo + (p.nlines - 1) * M + (p.L / M - 1) * p.blk + M;
+        e.out = oo + line_map_extent(p.ni, p.nlines, p.os_o, p.os_i, M) + (p.L / M - 1) * p.blk;
         break;
     }
     case P_STRIDED:
@@ -961,14 +1057,21 @@ Extent pass_extent(const Pass& p, size_t esz)
     case P_STRIDED_OSPLIT:
     case P_POISSON_X: {
         const long long g = p.groups - 1, c = p.cols - 1, d = p.fd.d;
+        // largest group offset on a side: g gs, or with a two-level map
+        // (g / gdiv) gs + (g % gdiv) gs2 <= (g / gdiv) gs + (min(groups, gdiv) - 1) gs2
+        auto gmax = [&](int gdiv, long long gs, long long gs2) -> long long {
+            if (gdiv > 1) return (g / gdiv) * gs + (std::min<long long>(p.groups, gdiv) - 1) * gs2;
+            return g * gs;
+        };
+        const long long gi = gmax(p.gdiv_in, p.gs_in, p.gs2_in), go = gmax(p.gdiv_out, p.gs_out, p.gs2_out);
         if (p.kind == P_STRIDED_SPLIT)
-            e.in = oi + g * p.gs_in + c + (p.L / d - 1) * p.blk + (d - 1) * p.es_in + 1;
+            e.in = oi + gi + c + (p.L / d - 1) * p.blk + (d - 1) * p.es_in + 1;
         else
-            e.in = oi + g * p.gs_in + c + (long long)(p.L - 1) * p.es_in + 1;
+            e.in = oi + gi + c + (long long)(p.L - 1) * p.es_in + 1;
         if (p.kind == P_STRIDED_OSPLIT)
-            e.out = oo + g * p.gs_out + c + (p.L / d - 1) * p.blk + (d - 1) * p.es_out + 1;
+            e.out = oo + go + c + (p.L / d - 1) * p.blk + (d - 1) * p.es_out + 1;
         else
-            e.out = oo + g * p.gs_out + c + (long long)(p.L - 1) * p.es_out + 1;
+            e.out = oo + go + c + (long long)(p.L - 1) * p.es_out + 1;
         break;
     }
     case P_R2C: // M pairs in, M + 1 complex out
@@ -1036,8 +1139,9 @@ int validate_extents(const Plan& plan)
         const std::vector<Pass>* v;
         const char* name;
         long long in, out;
-    } lists[] = {{&plan.fwd, "forward", sig, spec}, {&plan.inv, "inverse", spec, sig},
-                 {&plan.poisson, "poisson", sig, sig}};
+    } lists[] = {{&plan.fwd, "forward", sig, spec},         {&plan.inv, "inverse", spec, sig},
+                 {&plan.poisson, "poisson", sig, sig},         {&plan.fwd_ip, "in-place forward", sig, spec},
+                 {&plan.inv_ip, "in-place inverse", spec, sig}};
     for (const List& l : lists) {
         for (size_t k = 0; k < l.v->size(); ++k) {
             const Pass& p = (*l.v)[k];
@@ -1202,6 +1306,7 @@ int build_pencil(Plan& plan, unsigned /*flags*/)
     plan.pz_pack.kind = P_CONTIG_PACK;
     plan.pz_pack.fd = make_fastdiv((uint32_t)M);
     plan.pz_pack.blk = lines * M;
+    set_line_map(plan.pz_pack, (int)lines, 0, N2, 0, M); // line l at l M of each send block
     plan.pz_pack.src = B_IN;
     plan.pz_pack.dst = B_SEND;
     // standalone pack / unpack

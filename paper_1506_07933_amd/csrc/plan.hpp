@@ -50,6 +50,11 @@ struct Pass {
     int nt_in = 0; // strided: streaming loads (tiles read whole, aligned 128-byte lines)
     int nt_out = 0; // R2C / C2R z-pass: streaming stores (set by make_real_z from the output size)
     long long gs_in = 0, gs_out = 0, es_in = 0, es_out = 0;
+    // two-level group maps (blocked layouts): with gdiv > 1, group g at
+    // (g / gdiv) gs + (g % gdiv) gs2 on that side
+    int gdiv_in = 0, gdiv_out = 0;
+    long long gs2_in = 0, gs2_out = 0;
+    int fixedB = 0; // the layout fixes the tile width (a blocked intermediate): the tuner keeps it
     // pack / split
     FastDiv fd{1, 1ull << 32};
     long long blk = 0;
@@ -91,6 +96,11 @@ public:
     int cus = 256;  // compute units of the device (persistent grids)
     size_t esz = 8; // bytes per complex element
     std::vector<Pass> fwd, inv, poisson;
+    // With the blocked schedule (out of place only), fwd / inv pass through
+    // blocked intermediates; an in-place call (in == out) runs these lists,
+    // the transposed schedule, instead.  Empty otherwise.
+    std::vector<Pass> fwd_ip, inv_ip;
+    int blocked = 0; // block width (columns) of the blocked intermediates, 0: not used
     // pencil stages
     Pass pz, pz_pack, pk, upk, py, py_split;
     // slab stages (Algorithm 3) of one of slab_p tasks: forward z, y, y with

@@ -104,9 +104,12 @@ static std::string pass_key(const Plan& plan, const Pass& p, const char* arch)
                                "poisson", "pack",       "unpack",  "copy",           "poisson_x", "strided_pack"};
     std::ostringstream k;
     k << arch << "|" << (plan.prec == MIFFT_FP64 ? "fp64" : "fp32") << "|" << kn[p.kind] << "|L=" << p.L;
-    if (p.kind == P_STRIDED || p.kind == P_STRIDED_SPLIT)
+    if (p.kind == P_STRIDED || p.kind == P_STRIDED_SPLIT) {
         k << "|cols=" << p.cols << "|groups=" << p.groups << "|es=" << p.es_in << "/" << p.es_out
           << "|gs=" << p.gs_in << "/" << p.gs_out;
+        if (p.gdiv_in > 1 || p.gdiv_out > 1)
+            k << "|gdiv=" << p.gdiv_in << "/" << p.gdiv_out << "|gs2=" << p.gs2_in << "/" << p.gs2_out;
+    }
     else
         k << "|lines=" << p.nlines;
     return k.str();
@@ -131,6 +134,7 @@ static bool apply_choice(const Plan& plan, Pass& p, int vidx, int shape)
         const int B = shape;
         if (!pow2_in(B, 1, 64) || (long long)B * tpl > 1024 || (size_t)(B + 1) * p.L * esz > 160 * 1024)
             return false;
+        if (p.fixedB && B != p.fixedB) return false; // the tile width is part of a blocked layout
         int lg = 0;
         while ((1 << lg) < B) ++lg;
         p.vidx = vidx;
@@ -162,7 +166,9 @@ static std::vector<std::pair<int, int>> candidates(const Plan& plan, const Pass&
     for (int v = 0; v < variant_count(plan.prec); ++v) {
         if (variant_L(plan.prec, v) != Lv) continue;
         const int tpl = variant_tpl(plan.prec, v);
-        if (p.kind == P_STRIDED) {
+        if (p.kind == P_STRIDED && p.fixedB) {
+            out.push_back({v, p.fixedB});
+        } else if (p.kind == P_STRIDED) {
             for (int B : {4, 8, 16, 32, 64})
                 if ((long long)B * tpl >= 64 || B == 64) out.push_back({v, B});
         } else {
@@ -177,7 +183,7 @@ static std::vector<std::pair<int, int>> candidates(const Plan& plan, const Pass&
 static bool apply_wisdom_locked(Plan& plan, const char* arch)
 {
     bool all = true;
-    for (auto* list : {&plan.fwd, &plan.inv})
+    for (auto* list : {&plan.fwd, &plan.inv, &plan.fwd_ip, &plan.inv_ip})
         for (Pass& p : *list) {
             if (!is_tunable(p)) continue;
             auto it = g_wisdom.find(pass_key(plan, p, arch));
@@ -267,7 +273,7 @@ int tune_plan(Plan& plan)
             auto cap = [&](BufId b) { return (long long)((b == B_WS ? wbytes : bytes) / plan.esz); };
             return e.in <= cap(q.src) && e.out <= cap(q.dst);
         };
-        for (auto* list : {&plan.fwd, &plan.inv}) {
+        for (auto* list : {&plan.fwd, &plan.inv, &plan.fwd_ip, &plan.inv_ip}) {
             for (Pass& p : *list) {
                 if (!is_tunable(p)) continue;
                 const std::string key = pass_key(plan, p, arch);

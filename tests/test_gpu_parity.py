@@ -139,6 +139,7 @@ def test_chunked_schedule_matches_unchunked(monkeypatch, kind, prec):
         x = synth.normal_real(shape, np.float64, seed=11)
         ref = oracle.fft3d_r2c(x)
     res = {}
+    monkeypatch.setenv("MIFFT_BLOCKED", "0")  # the unchunked transposed schedule, not the blocked one
     for chunk in ("0", "4"):
         monkeypatch.setenv("MIFFT_CHUNK_MIB", chunk)
         p = Plan(shape, kind, prec)
@@ -154,6 +155,41 @@ def test_chunked_schedule_matches_unchunked(monkeypatch, kind, prec):
     n = float(np.prod(shape))
     x64 = x.astype(np.float64 if kind == "r2c" else np.complex128)
     report("chunked %s %s round trip" % (kind, prec), rel_l2(res["4"][1], n * x64), TOL[prec])
+
+
+@pytest.mark.parametrize("prec,shape", [("fp32", (96, 160, 512)), ("fp64", (256, 256, 256)),
+                                        ("fp32", (40, 64, 1024))])
+def test_blocked_schedule_out_of_place_and_in_place(prec, shape):
+    """Out of place, a C2C plan with the transposed intermediate passes
+    through blocked intermediates (z stores through the pack map, the strided
+    passes read contiguous blocks); in place it runs the transposed schedule.
+    Both match the oracle forward and inverse, and repeats are bitwise
+    equal."""
+    from paper_1506_07933_amd import Plan
+    cd = np.complex64 if prec == "fp32" else np.complex128
+    x = synth.uniform_complex(shape, cd, seed=21)
+    p = Plan(shape, "c2c", prec)
+    d = p.describe()
+    assert "forward kind=contig_pack" in d and "forward_inplace kind=contig " in d
+    ref = oracle.fft3d_c2c(x.astype(np.complex128), -1)
+    n = float(np.prod(shape))
+    xd = gpu(x)
+    yd = torch.empty_like(xd)
+    p.forward(xd, out=yd)
+    a = host(yd)
+    report("blocked %s %s forward" % (prec, shape), rel_l2(a, ref), TOL[prec])
+    p.forward(xd, out=yd)
+    np.testing.assert_array_equal(host(yd), a)
+    np.testing.assert_array_equal(host(xd), x)  # out of place leaves the input alone
+    zd = torch.empty_like(xd)
+    p.inverse(yd, out=zd)
+    report("blocked %s %s inverse" % (prec, shape), rel_l2(host(zd), n * x.astype(np.complex128)), TOL[prec])
+    wd = xd.clone()
+    p.forward(wd, out=wd)
+    report("in-place %s %s forward" % (prec, shape), rel_l2(host(wd), ref), TOL[prec])
+    p.inverse(wd, out=wd)
+    report("in-place %s %s inverse" % (prec, shape), rel_l2(host(wd), n * x.astype(np.complex128)), TOL[prec])
+    p.close()
 
 
 def test_inplace_matches_out_of_place_and_repeats_bitwise():

@@ -87,7 +87,115 @@ def test_512_cube_default_schedule_is_unchunked():
     passes, ws, _ = plan_only(512, 512, 512)
     assert ws == 512 ** 3 * 8
     assert [p["axis"] for p in passes if p["dir"] == "forward"] == ["z", "y", "x"]
-    assert [p["axis"] for p in passes if p["dir"] == "inverse"] == ["y", "x", "z"]
+    assert [p["axis"] for p in passes if p["dir"] == "inverse"] == ["z", "y", "x"]
+    # in-place calls run the transposed schedule
+    assert [p["axis"] for p in passes if p["dir"] == "forward_inplace"] == ["z", "y", "x"]
+    assert [p["axis"] for p in passes if p["dir"] == "inverse_inplace"] == ["y", "x", "z"]
+
+
+def test_512_cube_blocked_schedule_geometry():
+    """Out of place, the 512^3 complex64 transform passes through blocked
+    intermediates of 32-column (256-byte) blocks: z stores T[x][zb][y][zc]
+    through the pack map, y reads contiguous 512 x 32 blocks of T and writes
+    U[k1][zb][x][zc], x reads contiguous blocks of U and writes the standard
+    layout."""
+    passes, _, _ = plan_only(512, 512, 512)
+    z, y, x = [p for p in passes if p["dir"] == "forward"]
+    n, W = 512, 32
+    assert z["kind"] == "contig_pack" and z["pm"] == "%d/%d" % (W, n * W)
+    assert y["kind"] == x["kind"] == "strided"
+    assert y["B"] == x["B"] == y["cols"] == x["cols"] == str(W)
+    assert y["groups"] == x["groups"] == str(n * n // W)
+    # y: group g = x nb + zb at g n1 W (one contiguous block); row k1 at k1 n0 n2
+    # + zb n0 W + x W
+    assert y["es"] == "%d/%d" % (W, n * n) and y["gs"] == "%d/%d" % (n * W, W)
+    assert y["gdiv"] == "0/%d" % (n // W) and y["gs2"] == "0/%d" % (n * W) and y["nt"] == "1"
+    # x: group g = k1 nb + zb at g n0 W; row k0 of the output at k0 n1 n2 + g W
+    assert x["es"] == "%d/%d" % (W, n * n) and x["gs"] == "%d/%d" % (n * W, W)
+    assert x["gdiv"] == "0/0" and x["nt"] == "1"
+
+
+def _emulate(passes, x, nws):
+    """Run a plan's pass list on the CPU: every pass's index maps as the
+    kernels compute them (tiles, two-level group maps, the pack map), with a
+    numpy FFT per line."""
+    import numpy as np
+
+    def pair(v):
+        a, b = v.split("/")
+        return int(a), int(b)
+    bufs = {"in": x.copy(), "out": np.zeros_like(x), "ws": np.zeros(max(nws, 1), dtype=x.dtype)}
+    flow = [("in", "out"), ("out", "ws"), ("ws", "out")]
+    for k, p in enumerate(passes):
+        src, dst = flow[k]
+        S, D = bufs[src], bufs[dst]
+        L = int(p["L"])
+        fft = (lambda a: np.fft.fft(a, axis=-1)) if p["sgn"] == "1" else \
+              (lambda a: np.fft.ifft(a, axis=-1) * a.shape[-1])
+        if p["kind"] == "contig_pack":
+            M, blk = pair(p["pm"])
+            nl, ni = int(p["lines"]), int(p["ni"])
+            is_o, is_i = pair(p["is"])
+            os_o, os_i = pair(p["os"])
+            line = np.arange(nl)
+            lo, li = line // ni, line % ni
+            ib = lo * is_o + li * is_i
+            ob = lo * os_o + li * os_i
+            idx = np.arange(L)
+            q = idx // M
+            off = ob[:, None] + q[None, :] * blk + (idx - q * M)[None, :]
+            D[off.ravel()] = fft(S[ib[:, None] + idx[None, :]]).ravel()
+        else:
+            assert p["kind"] == "strided"
+            B, cols, groups, tpg, tiles = ints(p, "B", "cols", "groups", "tpg", "tiles")
+            es_in, es_out = pair(p["es"])
+            gs_in, gs_out = pair(p["gs"])
+            gd_in, gd_out = pair(p["gdiv"])
+            g2_in, g2_out = pair(p["gs2"])
+            tl = np.repeat(np.arange(tiles), B)
+            cc = np.tile(np.arange(B), tiles)
+            if tpg > 0:
+                g = tl // tpg
+                col = (tl - g * tpg) * B + cc
+                g = np.where(col >= cols, groups, g)
+            else:
+                f = tl * B + cc
+                g = f // cols
+                col = f - g * cols
+            ok = g < groups
+            g, col = g[ok], col[ok]
+
+            def goff(d, s1, s2):
+                return (g // d) * s1 + (g % d) * s2 if d > 1 else g * s1
+            ib = goff(gd_in, gs_in, g2_in) + col
+            ob = goff(gd_out, gs_out, g2_out) + col
+            r = np.arange(L)
+            D[ob[:, None] + r[None, :] * es_out] = fft(S[ib[:, None] + r[None, :] * es_in])
+    return bufs["out"]
+
+
+@pytest.mark.parametrize("shape,prec", [((8, 64, 512), 0), ((6, 40, 1024), 0), ((4, 32, 512), 1),
+                                         ((10, 96, 192), 1)])
+def test_blocked_schedule_maps_compose_to_the_3d_dft(shape, prec):
+    """The blocked schedule's index maps (pack map of the z-pass, tiles and
+    two-level group maps of the strided passes), followed on the CPU with a
+    library FFT per line, give the 3-D DFT forward and n0 n1 n2 times the
+    input back: every element is read from where the pass before wrote it."""
+    import numpy as np
+    passes, ws, _ = plan_only(*shape, prec=prec)
+    fwd = [p for p in passes if p["dir"] == "forward"]
+    inv = [p for p in passes if p["dir"] == "inverse"]
+    assert [p["kind"] for p in fwd] == ["contig_pack", "strided", "strided"]
+    assert [p["kind"] for p in inv] == ["contig_pack", "strided", "strided"]
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+    nws = ws // (16 if prec else 8)
+    ref = np.fft.fftn(x.reshape(shape)).ravel()
+    y = _emulate(fwd, x, nws)
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+    z = _emulate(inv, ref, nws)
+    assert np.linalg.norm(z - n * x) <= 1e-12 * np.linalg.norm(n * x)
 
 
 def test_512_cube_chunked_transposed_intermediate(monkeypatch):
