@@ -89,11 +89,7 @@ template <typename T, bool WAVE_LOCAL, bool OUT_PACK> struct ContigCtx {
         v.y *= sgn;
         if constexpr (OUT_PACK) {
             uint32_t q = fdiv((uint32_t)idx, pm);
-            V* p = out + ((long long)q * pblk + (idx - (int)(q * pm.d)));
-            if constexpr (MIFFT_CONTIG_NT)
-                store_nt<T>(p, v);
-            else
-                *p = v;
+            out[(long long)q * pblk + (idx - (int)(q * pm.d))] = v;
         } else if constexpr (MIFFT_CONTIG_NT) {
             store_nt<T>(out + idx, v);
         } else {

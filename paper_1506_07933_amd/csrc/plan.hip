@@ -342,8 +342,15 @@ void strided_grid(const Plan& plan, Pass& p)
         per_cu = (int)std::min<size_t>((size_t)160 * 1024 / std::max<size_t>(p.shmem, 1), 2048 / p.block);
         per_cu = std::max(per_cu, 1);
     }
+    // Resident grid, balanced: every workgroup walks the same number of tiles
+    // (rounds), so no round runs with a few workgroups while the rest of the
+    // device idles -- e.g. the 1032 tiles of the 256^3 R2C x-pass: 344
+    // workgroups of 3 tiles instead of 512 with 8 of them taking a third.
     const long long cap = (long long)plan.cus * per_cu;
-    if (ntiles > cap) p.grid = (unsigned)cap;
+    if (ntiles > cap) {
+        const long long rounds = (ntiles + cap - 1) / cap;
+        p.grid = (unsigned)((ntiles + rounds - 1) / rounds);
+    }
 }
 
 // ng > 1 (contiguous and strided passes): one launch over ng transforms of
@@ -767,10 +774,15 @@ static int strided_variant_for_B(const Plan& plan, int L, int B)
 static bool build_blocked(Plan& plan, int vz)
 {
     const int n0 = plan.n0, n1 = plan.n1, n2 = plan.n2;
-    const int W = (int)(256 / plan.esz);
-    if (plan.kind != MIFFT_C2C || vz < 0 || n0 < 2 || n1 < 2 || n2 % W != 0) return false;
-    if (const char* e = getenv("MIFFT_BLOCKED")) // "0": the transposed schedule (for comparison)
-        if (atoi(e) == 0) return false;
+    int wbytes = 256;
+    if (const char* e = getenv("MIFFT_BLOCK_BYTES")) wbytes = atoi(e);
+    if (wbytes != 64 && wbytes != 128 && wbytes != 256 && wbytes != 512) return false;
+    const int W = (int)(wbytes / (int)plan.esz);
+    if (W < 1 || plan.kind != MIFFT_C2C || vz < 0 || n0 < 2 || n1 < 2 || n2 % W != 0) return false;
+    // opt-in (MIFFT_BLOCKED=1): on the MI355X it measured the same as the
+    // transposed schedule (512^3 complex64 forward 1.203 vs 1.199 ms)
+    const char* be = getenv("MIFFT_BLOCKED");
+    if (!be || atoi(be) == 0) return false;
     const int vy = strided_variant_for_B(plan, n1, W), vx = strided_variant_for_B(plan, n0, W);
     if (vy < 0 || vx < 0) return false;
     const int nb = n2 / W;

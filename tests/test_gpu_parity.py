@@ -159,13 +159,14 @@ def test_chunked_schedule_matches_unchunked(monkeypatch, kind, prec):
 
 @pytest.mark.parametrize("prec,shape", [("fp32", (96, 160, 512)), ("fp64", (256, 256, 256)),
                                         ("fp32", (40, 64, 1024))])
-def test_blocked_schedule_out_of_place_and_in_place(prec, shape):
-    """Out of place, a C2C plan with the transposed intermediate passes
-    through blocked intermediates (z stores through the pack map, the strided
-    passes read contiguous blocks); in place it runs the transposed schedule.
-    Both match the oracle forward and inverse, and repeats are bitwise
-    equal."""
+def test_blocked_schedule_out_of_place_and_in_place(monkeypatch, prec, shape):
+    """With MIFFT_BLOCKED=1, out of place, a C2C plan with the transposed
+    intermediate passes through blocked intermediates (z stores through the
+    pack map, the strided passes read contiguous blocks); in place it runs the
+    transposed schedule.  Both match the oracle forward and inverse, and
+    repeats are bitwise equal."""
     from paper_1506_07933_amd import Plan
+    monkeypatch.setenv("MIFFT_BLOCKED", "1")
     cd = np.complex64 if prec == "fp32" else np.complex128
     x = synth.uniform_complex(shape, cd, seed=21)
     p = Plan(shape, "c2c", prec)

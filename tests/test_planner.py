@@ -77,7 +77,10 @@ def test_launch_shapes_cover_and_fit(shape, prec, kind):
                 # prefetching kernels walk the tiles with a grid of at most one
                 # resident wave of workgroups (256 CUs x workgroups per CU)
                 per_cu = max(1, min(160 * 1024 // lds, 2048 // block))
-                assert grid == min(tiles, 256 * per_cu)
+                cap = 256 * per_cu
+                rounds = -(-tiles // cap)
+                assert grid == -(-tiles // rounds)  # balanced: every workgroup walks `rounds` tiles
+                assert grid <= cap and grid * rounds >= tiles > grid * (rounds - 1)
             else:
                 assert grid == tiles
             assert lds == (B * L + L) * esz  # column tile + the twiddle table
@@ -87,19 +90,21 @@ def test_512_cube_default_schedule_is_unchunked():
     passes, ws, _ = plan_only(512, 512, 512)
     assert ws == 512 ** 3 * 8
     assert [p["axis"] for p in passes if p["dir"] == "forward"] == ["z", "y", "x"]
-    assert [p["axis"] for p in passes if p["dir"] == "inverse"] == ["z", "y", "x"]
-    # in-place calls run the transposed schedule
-    assert [p["axis"] for p in passes if p["dir"] == "forward_inplace"] == ["z", "y", "x"]
-    assert [p["axis"] for p in passes if p["dir"] == "inverse_inplace"] == ["y", "x", "z"]
+    assert [p["axis"] for p in passes if p["dir"] == "inverse"] == ["y", "x", "z"]
+    assert not [p for p in passes if p["dir"].endswith("_inplace")]
 
 
-def test_512_cube_blocked_schedule_geometry():
+def test_512_cube_blocked_schedule_geometry(monkeypatch):
     """Out of place, the 512^3 complex64 transform passes through blocked
     intermediates of 32-column (256-byte) blocks: z stores T[x][zb][y][zc]
     through the pack map, y reads contiguous 512 x 32 blocks of T and writes
     U[k1][zb][x][zc], x reads contiguous blocks of U and writes the standard
-    layout."""
+    layout.  In-place calls run the transposed schedule."""
+    monkeypatch.setenv("MIFFT_BLOCKED", "1")
     passes, _, _ = plan_only(512, 512, 512)
+    assert [p["axis"] for p in passes if p["dir"] == "inverse"] == ["z", "y", "x"]
+    assert [p["axis"] for p in passes if p["dir"] == "forward_inplace"] == ["z", "y", "x"]
+    assert [p["axis"] for p in passes if p["dir"] == "inverse_inplace"] == ["y", "x", "z"]
     z, y, x = [p for p in passes if p["dir"] == "forward"]
     n, W = 512, 32
     assert z["kind"] == "contig_pack" and z["pm"] == "%d/%d" % (W, n * W)
@@ -176,12 +181,13 @@ def _emulate(passes, x, nws):
 
 @pytest.mark.parametrize("shape,prec", [((8, 64, 512), 0), ((6, 40, 1024), 0), ((4, 32, 512), 1),
                                          ((10, 96, 192), 1)])
-def test_blocked_schedule_maps_compose_to_the_3d_dft(shape, prec):
+def test_blocked_schedule_maps_compose_to_the_3d_dft(monkeypatch, shape, prec):
     """The blocked schedule's index maps (pack map of the z-pass, tiles and
     two-level group maps of the strided passes), followed on the CPU with a
     library FFT per line, give the 3-D DFT forward and n0 n1 n2 times the
     input back: every element is read from where the pass before wrote it."""
     import numpy as np
+    monkeypatch.setenv("MIFFT_BLOCKED", "1")
     passes, ws, _ = plan_only(*shape, prec=prec)
     fwd = [p for p in passes if p["dir"] == "forward"]
     inv = [p for p in passes if p["dir"] == "inverse"]
