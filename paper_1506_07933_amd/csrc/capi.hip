@@ -381,7 +381,11 @@ static int run_passes(const Plan& cp, const std::vector<Pass>& list, const void*
         char* dst = (char*)res(q.dst);
         if (src) src += q.off_in;
         if (dst) dst += q.off_out;
-        hipError_t e = launch_pass(q, p.prec, src, dst, s);
+        char* nyq = (char*)res(q.nyq_buf);
+        if (q.nyq_buf != B_NONE && !nyq)
+            return set_error(MIFFT_ERR_INVALID, "internal: the Nyquist plane's buffer was not provided");
+        if (nyq) nyq += q.nyq_off;
+        hipError_t e = launch_pass(q, p.prec, src, dst, s, nyq);
         if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
         if (ev) hipEventRecord(ev[++qi], s);
     }
@@ -529,6 +533,7 @@ static Pass renamed(Pass q, BufId from, BufId to)
 {
     if (q.src == from) q.src = to;
     if (q.dst == from) q.dst = to;
+    if (q.nyq_buf == from) q.nyq_buf = to;
     return q;
 }
 
@@ -541,8 +546,10 @@ int mifft_spectral_apply(mifft_plan plan, int op, double alpha, const void* f, v
     if ((rc = check_field(f, "f")) || (rc = check_field(u, "u"))) return rc;
     if (f == u) return set_error(MIFFT_ERR_INVALID, "f and u must not overlap");
     std::vector<Pass> list = plan->poisson;
-    list[plan->poisson_mul].op = op;
-    list[plan->poisson_mul].alpha = alpha;
+    for (int k = 0; k < plan->poisson_mul_n; ++k) {
+        list[plan->poisson_mul + k].op = op;
+        list[plan->poisson_mul + k].alpha = alpha;
+    }
     char* w = (char*)(ws ? ws : plan->ws);
     const size_t half = plan->poisson_ws_bytes / 2;
     return run_passes(*plan, list, f, u, nullptr, w, w + half, (hipStream_t)stream);
@@ -580,7 +587,7 @@ int mifft_spectral_gradient(mifft_plan plan, const void* f, void* gx, void* gy, 
             if (g[j] == g[k]) return set_error(MIFFT_ERR_INVALID, "the outputs must be distinct");
     }
     const std::vector<Pass>& P = plan->poisson;
-    const int mi = plan->poisson_mul;
+    const int mi = plan->poisson_mul, nm = plan->poisson_mul_n;
     const Pass& M = P[mi];
     const BufId D = M.src;
     const BufId E = M.kind == P_POISSON_X ? (D == B_SEND ? B_RECV : B_SEND) : B_WS;
@@ -591,13 +598,15 @@ int mifft_spectral_gradient(mifft_plan plan, const void* f, void* gx, void* gy, 
     if ((rc = run_passes(*plan, fwd, f, nullptr, w + 2 * half, w, w + half, s))) return rc;
     for (int j = 0; j < 3; ++j) {
         std::vector<Pass> list;
-        Pass m = M;
-        m.src = D;
-        m.dst = E;
-        m.op = MIFFT_OP_DX + j;
-        m.acc = 0;
-        list.push_back(m);
-        for (size_t k = mi + 1; k < P.size(); ++k) list.push_back(renamed(P[k], D, E));
+        for (int k = 0; k < nm; ++k) { // the multiply: D -> E
+            Pass m = P[mi + k];
+            m.src = D;
+            m.dst = E;
+            m.op = MIFFT_OP_DX + j;
+            m.acc = 0;
+            list.push_back(m);
+        }
+        for (size_t k = mi + nm; k < P.size(); ++k) list.push_back(renamed(P[k], D, E));
         if ((rc = run_passes(*plan, list, nullptr, g[j], w + 2 * half, w, w + half, s))) return rc;
     }
     return MIFFT_OK;
@@ -615,7 +624,7 @@ int mifft_spectral_divergence(mifft_plan plan, const void* vx, const void* vy, c
     if (d == vx || d == vy || d == vz) return set_error(MIFFT_ERR_INVALID, "d must not overlap the inputs");
     const void* v[3] = {vx, vy, vz};
     const std::vector<Pass>& P = plan->poisson;
-    const int mi = plan->poisson_mul;
+    const int mi = plan->poisson_mul, nm = plan->poisson_mul_n;
     const Pass& M = P[mi];
     const BufId D = M.src;
     char* w = (char*)(ws ? ws : plan->ws);
@@ -623,16 +632,18 @@ int mifft_spectral_divergence(mifft_plan plan, const void* vx, const void* vy, c
     hipStream_t s = (hipStream_t)stream;
     for (int j = 0; j < 3; ++j) {
         std::vector<Pass> list(P.begin(), P.begin() + mi);
-        Pass m = M;
-        m.src = D;
-        m.dst = B_WS;
-        m.op = MIFFT_OP_DX + j;
-        m.acc = j > 0;
-        list.push_back(m);
+        for (int k = 0; k < nm; ++k) { // the multiply: D -> C (the third buffer), summed over j
+            Pass m = P[mi + k];
+            m.src = D;
+            m.dst = B_WS;
+            m.op = MIFFT_OP_DX + j;
+            m.acc = j > 0;
+            list.push_back(m);
+        }
         if ((rc = run_passes(*plan, list, v[j], nullptr, w + 2 * half, w, w + half, s))) return rc;
     }
     std::vector<Pass> inv;
-    for (size_t k = mi + 1; k < P.size(); ++k) inv.push_back(renamed(P[k], D, B_WS));
+    for (size_t k = mi + nm; k < P.size(); ++k) inv.push_back(renamed(P[k], D, B_WS));
     return run_passes(*plan, inv, nullptr, d, w + 2 * half, w, w + half, s);
 }
 

@@ -498,6 +498,7 @@ template <typename T> struct PoissonXArgs {
     int n1, nc, n2;
     int op, acc;
     T scale, alpha;
+    int k2_fixed; // >= 0: every column is (k1, k2) = (column, k2_fixed) (a single k2 plane, [x][k1])
 };
 
 // PHASE 0: the forward transform; the first stage reads global memory and
@@ -616,7 +617,8 @@ __global__ __launch_bounds__((poisson_tile_B<T, L, TPL>() * TPL),
     c0.es = a.es;
     c0.n0 = L;
     c0.op = a.op;
-    c0.col = spectral_col<T>(a.op, g + col / a.nc, col % a.nc, a.n1, a.n2, a.scale);
+    c0.col = a.k2_fixed >= 0 ? spectral_col<T>(a.op, col, a.k2_fixed, a.n1, a.n2, a.scale)
+                             : spectral_col<T>(a.op, g + col / a.nc, col % a.nc, a.n1, a.n2, a.scale);
     c0.scale = a.scale;
     c0.alpha = a.alpha;
     LineFFT<T, L, TPL, decltype(c0), RLt>::run(c0);
@@ -640,6 +642,10 @@ template <typename T> struct RealArgs {
     const cx<T>* tw;  // half-length twiddles
     const cx<T>* tw2; // exp(-2 pi i k / n2)
     int nt_out;       // streaming stores of the outputs
+    // With nyq set, element M = n2/2 of the complex side (the Nyquist plane)
+    // is not in the line but at nyq[lo * nyq_o + li * nyq_i] (a plane of its own).
+    cx<T>* nyq;
+    long long nyq_o, nyq_i;
     int nlines;
     int lines_per_wg;
     int ni;
@@ -676,7 +682,9 @@ __global__ __launch_bounds__(1024) void k_r2c_z(RealArgs<T> a)
         V s = cadd(za, zb);
         V p = cmul(a.tw2[k], csub(za, zb));
         const V r{half * (s.x + p.y), half * (s.y - p.x)};
-        if (a.nt_out)
+        if (k == L && a.nyq)
+            a.nyq[lo * a.nyq_o + li * a.nyq_i] = r;
+        else if (a.nt_out)
             store_nt<T>(out + k, r);
         else
             out[k] = r;
@@ -714,7 +722,7 @@ __global__ __launch_bounds__(1024) void k_c2r_z(RealArgs<T> a)
 #pragma unroll
             for (int i = 0; i < NK; ++i) {
                 const int k = c.t + i * TPL;
-                if (k <= L) v[i] = in[k];
+                if (k <= L) v[i] = (k == L && a.nyq) ? a.nyq[lo * a.nyq_o + li * a.nyq_i] : in[k];
             }
 #pragma unroll
             for (int i = 0; i < NK; ++i) {
@@ -722,7 +730,8 @@ __global__ __launch_bounds__(1024) void k_c2r_z(RealArgs<T> a)
                 if (k <= L) c.lds[lds_pad(k)] = v[i];
             }
         } else {
-            for (int k = c.t; k <= L; k += TPL) c.lds[lds_pad(k)] = in[k];
+            for (int k = c.t; k <= L; k += TPL)
+                c.lds[lds_pad(k)] = (k == L && a.nyq) ? a.nyq[lo * a.nyq_o + li * a.nyq_i] : in[k];
         }
     }
     c.sync();

@@ -357,7 +357,7 @@ void strided_grid(const Plan& plan, Pass& p)
 // the same shape, member i reading gsrc[i] and writing gdst[i] (blockIdx.y).
 template <typename T>
 static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStream_t s, int ng = 1,
-                             const void* const* gsrc = nullptr, void* const* gdst = nullptr)
+                             const void* const* gsrc = nullptr, void* const* gdst = nullptr, void* nyq = nullptr)
 {
     const Variant<T>& v = table<T>()[p.vidx];
     using V = cx<T>;
@@ -443,6 +443,7 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.acc = p.acc;
         a.scale = (T)p.scale;
         a.alpha = (T)p.alpha;
+        a.k2_fixed = p.k2_fixed;
         ensure_lds(reinterpret_cast<const void*>(v.poisson_x), p.shmem);
         hipLaunchKernelGGL(v.poisson_x, dim3(p.grid), dim3(p.block), p.shmem, s, a);
         break;
@@ -455,6 +456,9 @@ static hipError_t launch_fft(const Pass& p, const void* src, void* dst, hipStrea
         a.tw = (const V*)p.tw;
         a.tw2 = (const V*)p.tw2;
         a.nt_out = p.nt_out;
+        a.nyq = p.nyq_buf != B_NONE ? (V*)nyq : nullptr;
+        a.nyq_o = p.nyq_o;
+        a.nyq_i = p.nyq_i;
         a.nlines = (int)p.nlines;
         a.lines_per_wg = p.lines_per_wg;
         a.ni = p.ni;
@@ -488,10 +492,10 @@ hipError_t launch_pass_group(const Pass& p, int prec, int ng, const void* const*
     return launch_fft<float>(p, src[0], dst[0], s, ng, src, dst);
 }
 
-hipError_t launch_pass(const Pass& p, int prec, const void* src, void* dst, hipStream_t s)
+hipError_t launch_pass(const Pass& p, int prec, const void* src, void* dst, hipStream_t s, void* nyq)
 {
-    if (prec == MIFFT_FP64) return launch_fft<double>(p, src, dst, s);
-    return launch_fft<float>(p, src, dst, s);
+    if (prec == MIFFT_FP64) return launch_fft<double>(p, src, dst, s, 1, nullptr, nullptr, nyq);
+    return launch_fft<float>(p, src, dst, s, 1, nullptr, nullptr, nyq);
 }
 
 // --------------------------------------------------------------- twiddles
@@ -1165,6 +1169,14 @@ int validate_extents(const Plan& plan)
                 return set_error(MIFFT_ERR_INVALID,
                                  "internal: %s pass %zu reaches %lld / %lld elements of buffers holding %lld / %lld",
                                  l.name, k, e.in, e.out, cap(p.src), cap(p.dst));
+            if (p.nyq_buf != B_NONE) { // the Nyquist plane of a real z-pass
+                const long long lo = p.ni < p.nlines ? (p.nlines - 1) / p.ni : 0;
+                const long long li = std::min<long long>(p.ni, p.nlines) - 1;
+                const long long ne = p.nyq_off / esz + lo * p.nyq_o + li * p.nyq_i + 1;
+                if (ne > cap(p.nyq_buf))
+                    return set_error(MIFFT_ERR_INVALID, "internal: %s pass %zu reaches %lld of %lld Nyquist elements",
+                                     l.name, k, ne, cap(p.nyq_buf));
+            }
         }
     }
     return MIFFT_OK;
@@ -1184,6 +1196,7 @@ void rebuild_poisson(Plan& plan)
     plan.poisson.clear();
     plan.poisson_ws_bytes = plan.spectral_ws_bytes = 0;
     plan.poisson_mul = -1;
+    plan.poisson_mul_n = 1;
     if (plan.kind != MIFFT_R2C) return;
     const int nc = plan.n2 / 2 + 1;
     const size_t half_bytes = (size_t)plan.n0 * plan.n1 * nc * plan.esz;
@@ -1198,21 +1211,50 @@ void rebuild_poisson(Plan& plan)
     const char* unfused = getenv("MIFFT_POISSON_UNFUSED"); // "1": keep the standalone multiply
     if (plan.n0 > 1 && fx && !(unfused && atoi(unfused) != 0)) {
         const bool T = plan.transposed;
+        const int M = plan.n2 / 2;
+        // Nyquist plane on its own (transposed intermediate, rows of M whole
+        // 128-byte lines): the z-pass stores the k2 = n2/2 plane as N[x][k1]
+        // after W and the main passes transform exactly M columns (no ragged
+        // 257th / 129th column); the plane's own chain -- y (contiguous lines
+        // of N), fused x with k2 = n2/2, y^-1 -- runs beside them.
+        bool split = T && plan.n1 > 1 && ((size_t)M * plan.esz) % 128 == 0;
+        if (const char* e = getenv("MIFFT_POISSON_NYQ")) // "0": the 257th column in the rows (comparison)
+            split = split && atoi(e) != 0;
+        const int vyc = split ? contig_variant(plan.prec, plan.n1) : -1;
+        if (split && vyc < 0) split = false;
         // both buffers are internal: with the transposed intermediate their
         // rows are padded to ncw (128-byte multiples), as W's are
-        const int pitch = T ? plan.ncw : nc;
+        const int pitch = split ? M : T ? plan.ncw : nc;
+        const int cols = split ? M : nc;
         const long long plane = (long long)plan.n1 * pitch;
-        const int M = plan.n2 / 2;
-        Pass z = plan.fwd[0];
+        const long long noff = (long long)plan.n0 * plan.n1 * pitch * (long long)plan.esz; // N after W (bytes)
+        const BufId D = T ? B_RECV : B_SEND; // where the spectrum sits from the y-pass on
+        const long long lines = (long long)plan.n0 * plan.n1;
+        int rc = 0;
+        Pass z, yn; // (declared before the first jump to the fallback)
+        // the z-passes over all lines (the forward / inverse lists may be chunked)
+        if ((rc = make_real_z(plan, z, P_R2C, lines))) goto fallback;
         set_line_map(z, (int)z.nlines, 0, M, 0, pitch); // reals -> A, rows of `pitch`
         z.src = B_IN;
         z.dst = B_SEND;
+        if (split) { // line l = x n1 + y: N[l]
+            z.nyq_buf = D;
+            z.nyq_off = noff;
+            z.nyq_o = 0;
+            z.nyq_i = 1;
+        }
         plan.poisson.push_back(z);
-        const BufId D = T ? B_RECV : B_SEND; // where the spectrum sits from the y-pass on
-        int rc = 0;
+        if (split) { // the Nyquist plane's y-lines: contiguous rows of N[x][k1]
+            rc = make_contig(plan, yn, plan.n1, plan.n0, vyc);
+            if (rc) goto fallback;
+            yn.sgn = +1;
+            yn.tag = 1;
+            yn.src = yn.dst = D;
+            yn.off_in = yn.off_out = noff;
+        }
         if (plan.n1 > 1) {
             Pass y;
-            rc = make_strided(plan, y, plan.n1, nc, plan.n0, pitch, plane, plan.fwd[1].vidx, 0);
+            rc = make_strided(plan, y, plan.n1, cols, plan.n0, pitch, plane, plan.fwd[1].vidx, 0);
             if (rc) goto fallback;
             if (T) { // A -> W[k1][x][k2]
                 y.es_out = (long long)plan.n0 * pitch;
@@ -1224,6 +1266,7 @@ void rebuild_poisson(Plan& plan)
             y.dst = D;
             plan.poisson.push_back(y);
         }
+        if (split) plan.poisson.push_back(yn);
         {
             // fused x, in place: the default variant of the length (the most
             // threads per line) and the tile width its kernel is compiled for
@@ -1231,7 +1274,7 @@ void rebuild_poisson(Plan& plan)
             int vp = default_variant(plan.prec, plan.n0);
             if (vp < 0) vp = vx;
             if (T)
-                rc = make_strided(plan, x, plan.n0, nc, plan.n1, pitch, (long long)plan.n0 * pitch, vp, 1);
+                rc = make_strided(plan, x, plan.n0, cols, plan.n1, pitch, (long long)plan.n0 * pitch, vp, 1);
             else
                 rc = make_strided(plan, x, plan.n0, (int)plane, 1, plane, 0, vp, 1);
             if (rc) goto fallback;
@@ -1244,14 +1287,38 @@ void rebuild_poisson(Plan& plan)
             x.scale = scale;
             x.tag = 2;
             x.src = x.dst = D;
+            plan.poisson_mul = (int)plan.poisson.size();
             plan.poisson.push_back(x);
+            if (split) { // the Nyquist plane: lines along x (stride n1), columns k1, k2 = n2/2
+                Pass xn;
+                rc = make_strided(plan, xn, plan.n0, plan.n1, 1, plan.n1, 0, vp, 1);
+                if (rc) goto fallback;
+                set_tile_width(xn, plan.prec, variant_tpl(plan.prec, vp), variant_poisson_B(plan.prec, vp));
+                xn.kind = P_POISSON_X;
+                xn.n0 = plan.n0;
+                xn.n1 = plan.n1;
+                xn.n2c = plan.n1;
+                xn.nz = plan.n2;
+                xn.k2_fixed = M;
+                xn.scale = scale;
+                xn.tag = 2;
+                xn.src = xn.dst = D;
+                xn.off_in = xn.off_out = noff;
+                plan.poisson.push_back(xn);
+                plan.poisson_mul_n = 2;
+            }
+        }
+        if (split) {
+            Pass yni = yn;
+            yni.sgn = -1;
+            plan.poisson.push_back(yni);
         }
         if (plan.n1 > 1) {
             Pass y;
             const int vy = plan.fwd[1].vidx;
             // transposed: lines along k1 of W (stride n0 pitch); groups = x, columns = k2
-            rc = T ? make_strided(plan, y, plan.n1, nc, plan.n0, (long long)plan.n0 * pitch, pitch, vy, 0)
-                   : make_strided(plan, y, plan.n1, nc, plan.n0, pitch, plane, vy, 0);
+            rc = T ? make_strided(plan, y, plan.n1, cols, plan.n0, (long long)plan.n0 * pitch, pitch, vy, 0)
+                   : make_strided(plan, y, plan.n1, cols, plan.n0, pitch, plane, vy, 0);
             if (rc) goto fallback;
             y.sgn = -1;
             y.tag = 1;
@@ -1259,14 +1326,24 @@ void rebuild_poisson(Plan& plan)
             plan.poisson.push_back(y);
         }
         {
-            Pass zi = plan.inv.back(); // C2R; with the transposed intermediate, in W's line order
-            if (!T) set_line_map(zi, (int)zi.nlines, 0, pitch, 0, M);
+            Pass zi; // C2R; with the transposed intermediate, in W's line order
+            if ((rc = make_real_z(plan, zi, P_C2R, lines))) goto fallback;
+            if (!T)
+                set_line_map(zi, (int)zi.nlines, 0, pitch, 0, M);
+            else
+                set_line_map(zi, plan.n0, (long long)plan.n0 * pitch, pitch, M, (long long)plan.n1 * M);
             zi.src = D;
             zi.dst = B_OUT;
+            if (split) { // line (lo, li) = (y, x): N[x n1 + y]
+                zi.nyq_buf = D;
+                zi.nyq_off = noff;
+                zi.nyq_o = 1;
+                zi.nyq_i = plan.n1;
+            }
             plan.poisson.push_back(zi);
         }
-        plan.poisson_mul = (int)plan.poisson.size() - 1 - (plan.n1 > 1 ? 2 : 1);
-        plan.poisson_ws_bytes = 2 * (size_t)plan.n0 * plan.n1 * pitch * plan.esz;
+        // each half holds W (rows of `pitch`) and, split, the Nyquist plane
+        plan.poisson_ws_bytes = 2 * (size_t)plan.n0 * plan.n1 * (pitch + (split ? 1 : 0)) * plan.esz;
         plan.spectral_ws_bytes = plan.poisson_ws_bytes / 2 * 3;
         if (plan.spectral_ws_bytes > plan.default_ws_bytes) plan.default_ws_bytes = plan.spectral_ws_bytes;
         return;

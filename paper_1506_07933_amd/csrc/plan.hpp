@@ -55,6 +55,11 @@ struct Pass {
     int gdiv_in = 0, gdiv_out = 0;
     long long gs2_in = 0, gs2_out = 0;
     int fixedB = 0; // the layout fixes the tile width (a blocked intermediate): the tuner keeps it
+    // R2C / C2R z-pass: element n2/2 of line (lo, li) at nyq_buf + nyq_off
+    // (bytes) + (lo nyq_o + li nyq_i) elements, a plane of its own
+    BufId nyq_buf = B_NONE;
+    long long nyq_off = 0, nyq_o = 0, nyq_i = 0;
+    int k2_fixed = -1; // fused spectral x-pass over one k2 plane [x][k1]: every column is (k1, k2_fixed)
     // pack / split
     FastDiv fd{1, 1ull << 32};
     long long blk = 0;
@@ -120,6 +125,7 @@ public:
     size_t poisson_ws_bytes = 0;  // two half-spectrum buffers (Poisson solve, one operator)
     size_t spectral_ws_bytes = 0; // three (gradient, divergence)
     int poisson_mul = -1;         // index of the multiply pass in `poisson`
+    int poisson_mul_n = 1;        // multiply passes from there (2 with the Nyquist plane on its own)
     // opt-in per-pass event timing
     std::vector<hipEvent_t> prof_events; // max_calls * (max passes + 1)
     int prof_max_calls = 0, prof_calls = 0, prof_stride = 0, prof_npass = 0;
@@ -172,7 +178,8 @@ void set_line_map(Pass& p, int ni, long long is_o, long long is_i, long long os_
 void set_strided_geometry(Pass& p, int prec, int tpl, int L, int cols, int groups, int forceB);
 
 // Enqueue one pass with resolved buffers.
-hipError_t launch_pass(const Pass& p, int prec, const void* src, void* dst, hipStream_t s);
+// `nyq`: the resolved nyq_buf + nyq_off of the pass, if it has one.
+hipError_t launch_pass(const Pass& p, int prec, const void* src, void* dst, hipStream_t s, void* nyq = nullptr);
 // The same contiguous or strided pass of ng <= kMaxGroup transforms of one
 // shape as one launch (member i: src[i] -> dst[i]).
 hipError_t launch_pass_group(const Pass& p, int prec, int ng, const void* const* src, void* const* dst,

@@ -243,18 +243,44 @@ def test_small_grid_keeps_standard_layout():
             assert a == b
 
 
-def test_r2c_workspace_sizes():
+def test_r2c_workspace_sizes(monkeypatch):
     # transposed intermediate: rows of the half spectrum (129) padded to a
     # multiple of 128 bytes (136 complex128)
     passes, ws, pws = plan_only(256, 256, 256, kind=1, prec=1)
     w = 256 * 256 * 136 * 16
-    assert ws == w and pws == 2 * w
+    assert ws == w
     fwd = [p for p in passes if p["dir"] == "forward"]
     assert fwd[1]["es"] == "129/%d" % (256 * 136) and fwd[1]["gs"] == "%d/136" % (256 * 129)
     assert fwd[2]["es"] == "136/%d" % (256 * 129) and fwd[2]["gs"] == "%d/129" % (256 * 136)
+    # the spectral chain keeps the Nyquist plane apart: each Poisson half holds
+    # rows of exactly 128 complex128 and the 256 x 256 plane
+    assert pws == 2 * 256 * 256 * (128 + 1) * 16
+    # with the Nyquist column in the rows: the padded rows
+    monkeypatch.setenv("MIFFT_POISSON_NYQ", "0")
+    _, _, pws = plan_only(256, 256, 256, kind=1, prec=1)
+    assert pws == 2 * w
     # small grids keep the standard layout and the unpadded workspace
     _, ws, pws = plan_only(32, 32, 32, kind=1, prec=1)
     assert pws == 2 * 32 * 32 * 17 * 16
+
+
+def test_poisson_chain_with_the_nyquist_plane_apart():
+    """512^3 R2C: the fused spectral chain transforms rows of exactly 256
+    columns (8 column tiles of 32 per group for y, 16 of 16 for the fused x)
+    and runs the k2 = 256 plane N[x][k1] through its own y, fused x
+    (k2 fixed) and y^-1 passes, after W in the same half of the workspace."""
+    passes, _, pws = plan_only(512, 512, 512, kind=1, prec=0)
+    po = [p for p in passes if p["dir"] == "poisson"]
+    assert [(p["kind"], p["axis"]) for p in po] == [
+        ("r2c_z", "z"), ("strided", "y"), ("contig", "y"), ("poisson_x", "x"), ("poisson_x", "x"),
+        ("contig", "y"), ("strided", "y"), ("c2r_z", "z")]
+    noff = 512 * 512 * 256 * 8
+    assert po[1]["cols"] == "256" and po[1]["tiles"] == str(512 * 8)
+    assert po[3]["cols"] == "256" and po[3]["tiles"] == str(512 * 16)
+    assert po[2]["off"] == po[4]["off"] == po[5]["off"] == "%d/%d" % (noff, noff)
+    assert po[4]["cols"] == "512" and po[4]["groups"] == "1" and po[4]["es"] == "512/512"
+    assert po[2]["lines"] == "512" and po[2]["L"] == "512"
+    assert pws == 2 * (noff + 512 * 512 * 8)
 
 
 def test_plan_only_cannot_execute():
@@ -325,10 +351,13 @@ def test_pencil_plan_only_describes_fused_stages():
 
 
 @pytest.mark.parametrize("shape,transposed", [((512, 512, 512), True), ((64, 48, 32), False)])
-def test_poisson_fuses_the_x_passes(shape, transposed):
+def test_poisson_fuses_the_x_passes(monkeypatch, shape, transposed):
     """R2C Poisson: z, y, fused x-forward * multiply * x-inverse, y^-1, z^-1
     (5 passes, the spectrum read and written once per pass) instead of
-    7 passes plus the standalone multiply."""
+    7 passes plus the standalone multiply.  (Here with the Nyquist column in
+    the rows; the default splits it off for the transposed layout, see
+    test_poisson_chain_with_the_nyquist_plane_apart.)"""
+    monkeypatch.setenv("MIFFT_POISSON_NYQ", "0")
     passes, _, pws = plan_only(*shape, kind=1, prec=0)
     po = [p for p in passes if p["dir"] == "poisson"]
     assert [p["kind"] for p in po] == ["r2c_z", "strided", "poisson_x", "strided", "c2r_z"]
