@@ -88,12 +88,26 @@ def kernels_table(trace_dir, fetch_dir, write_dir, copy_fetch, copy_write, alg, 
     def short(name):
         return name.split("(")[0].replace("void ", "")
 
+    def grid(r):
+        return r.get("Grid_Size") or r.get("Grid_Size_X") or ""
+
+    # a kernel launched with more than one grid (e.g. the fused spectral pass
+    # over the main array and over the Nyquist plane) gets one row per grid
+    grids = {}
+    for r in trace:
+        if "mifft::k_" in r["Kernel_Name"]:
+            grids.setdefault(short(r["Kernel_Name"]), set()).add(grid(r))
+
+    def name_of(r):
+        k = short(r["Kernel_Name"])
+        return "%s [grid %s]" % (k, grid(r)) if len(grids.get(k, ())) > 1 else k
+
     def by_kernel(rows, key):
         d = {}
         for r in rows:
             if "mifft::k_" not in r["Kernel_Name"]:
                 continue
-            d.setdefault(short(r["Kernel_Name"]), []).append(key(r))
+            d.setdefault(name_of(r), []).append(key(r))
         return d
 
     dur = by_kernel(trace, lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
