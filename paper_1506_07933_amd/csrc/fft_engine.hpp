@@ -222,6 +222,13 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t k, FastDiv f)
 template <typename C, typename = void> struct ctx_prefetches : std::false_type {};
 template <typename C>
 struct ctx_prefetches<C, std::void_t<decltype(C::kPrefetch)>> : std::integral_constant<bool, C::kPrefetch> {};
+// Contexts that declare kRegOut = true take the last stage's results as
+// final_put_slot(slot, idx, v), slot = i R + r numbered as in FirstStageShape
+// (the last stage of a Stockham transform writes elements j + r L/R, the
+// set the first stage of a transform with that radix first reads).
+template <typename C, typename = void> struct ctx_reg_out : std::false_type {};
+template <typename C>
+struct ctx_reg_out<C, std::void_t<decltype(C::kRegOut)>> : std::integral_constant<bool, C::kRegOut> {};
 
 // The first stage's input positions: thread t reads, for its butterflies
 // i = 0 .. NB-1 (j = t + i TPL < L/R) and r = 0 .. R-1, element j + r L/R
@@ -285,7 +292,12 @@ struct Stage {
                 Bfly<R>::fwd(v[i]);
                 if constexpr (LAST) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) c.final_put(j + r * NBF, v[i][r]);
+                    for (int r = 0; r < R; ++r) {
+                        if constexpr (ctx_reg_out<Ctx>::value)
+                            c.final_put_slot(i * R + r, j + r * NBF, v[i][r]);
+                        else
+                            c.final_put(j + r * NBF, v[i][r]);
+                    }
                 } else {
                     const int base = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
@@ -307,6 +319,17 @@ template <int R0, int... Rest> struct FirstRadix<RadixList<R0, Rest...>> {
 };
 template <> struct FirstRadix<RadixList<>> {
     static constexpr int value = 1; // length 1: no stage
+};
+// The radices in reverse order (a Stockham transform may take its factors in
+// any order).
+template <typename A, typename B> struct RLConcat;
+template <int... A, int... B> struct RLConcat<RadixList<A...>, RadixList<B...>> {
+    using type = RadixList<A..., B...>;
+};
+template <typename RLt> struct ReverseRL;
+template <> struct ReverseRL<RadixList<>> { using type = RadixList<>; };
+template <int R0, int... Rest> struct ReverseRL<RadixList<R0, Rest...>> {
+    using type = typename RLConcat<typename ReverseRL<RadixList<Rest...>>::type, RadixList<R0>>::type;
 };
 
 

@@ -51,6 +51,11 @@ template <typename T> __device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v
 #ifndef MIFFT_NT_LOADS
 #define MIFFT_NT_LOADS 1
 #endif
+// The fused spectral x-pass hands its spectrum from the forward to the
+// inverse transform through the LDS tile (1) instead of registers (0).
+#ifndef MIFFT_POISSON_LDS_HANDOFF
+#define MIFFT_POISSON_LDS_HANDOFF 0
+#endif
 template <typename T> __device__ __forceinline__ cx<T> load_in(const cx<T>* p)
 {
     if constexpr (MIFFT_NT_LOADS) {
@@ -508,10 +513,17 @@ template <typename T> struct PoissonXArgs {
 // PHASE 1: the inverse transform (of the conjugate) reads the line from LDS
 // and stores the conjugate of its result.  B (columns per tile) is a
 // compile-time constant, so the LDS offsets of a thread's elements are
-// constants from one base address.
-template <typename T, int PHASE, int B> struct PoissonCtx {
+// constants from one base address.  With REG the spectrum passes from one
+// transform to the other in registers: the forward's last stage leaves its
+// results in mid[] and the inverse, whose radix order is the forward's
+// reversed, takes its first stage's inputs from there (the same elements,
+// in the same threads).
+template <typename T, int PHASE, int B, int SLOTS = 1, bool REG = false> struct PoissonCtx {
     using V = cx<T>;
-    static constexpr bool kSyncAfterFirstRead = PHASE == 1; // the first stage reads the LDS tile
+    static constexpr bool kSyncAfterFirstRead = PHASE == 1 && !REG; // the first stage reads the LDS tile
+    static constexpr bool kRegOut = PHASE == 0 && REG;
+    static constexpr bool kPrefetch = PHASE == 1 && REG;
+    V mid[REG ? SLOTS : 1];
     const V* src;
     V* data;
     V* lds; // column c of the tile: element idx at lds[idx * B]
@@ -532,6 +544,14 @@ template <typename T, int PHASE, int B> struct PoissonCtx {
             return valid ? src[(long long)idx * es] : V{T(0), T(0)};
         else
             return lds[idx * B];
+    }
+    __device__ __forceinline__ V first_get(int slot) const { return mid[slot]; }
+    template <int L, int TPL, int R> __device__ __forceinline__ void prefetch_next() {}
+    __device__ __forceinline__ void final_put_slot(int slot, int idx, V v)
+    {
+        v = spectral_mul<T>(op, idx, n0, col, scale, alpha, v);
+        v.y = -v.y;
+        mid[slot] = v;
     }
     __device__ __forceinline__ V lds_get(int idx) const { return lds[idx * B]; }
     __device__ __forceinline__ void lds_put(int idx, V v) { lds[idx * B] = v; }
@@ -605,8 +625,13 @@ __global__ __launch_bounds__((poisson_tile_B<T, L, TPL>() * TPL),
         g = (int)(f / (unsigned)a.cols);
         col = (int)(f - (unsigned)g * (unsigned)a.cols);
     }
+    // the inverse takes the radices in reverse order, so that its first stage
+    // reads the elements the forward's last stage leaves in each thread
+    constexpr bool REG = L > 1 && !MIFFT_POISSON_LDS_HANDOFF;
+    using RLi = typename ReverseRL<RLt>::type;
+    using Shape = FirstStageShape<L, TPL, FirstRadix<RLi>::value>;
     const V* twd = stage_twiddles<T>(a.tw, L, smem + B * L);
-    PoissonCtx<T, 0, B> c0;
+    PoissonCtx<T, 0, B, Shape::SLOTS, REG> c0;
     c0.valid = g < a.groups;
     const long long off = (long long)g * a.gs + col;
     c0.src = a.src + off;
@@ -622,8 +647,15 @@ __global__ __launch_bounds__((poisson_tile_B<T, L, TPL>() * TPL),
     c0.scale = a.scale;
     c0.alpha = a.alpha;
     LineFFT<T, L, TPL, decltype(c0), RLt>::run(c0);
-    __syncthreads(); // the multiplied spectrum of every column is in the tile
-    PoissonCtx<T, 1, B> c1;
+    // Without REG the multiplied spectrum of every column is in the tile.
+    // With it, no barrier: the forward's last stage synchronised after its
+    // LDS reads, so the inverse's first stage may write the tile.
+    if constexpr (!REG) __syncthreads();
+    PoissonCtx<T, 1, B, Shape::SLOTS, REG> c1;
+    if constexpr (REG) {
+#pragma unroll
+        for (int s = 0; s < Shape::SLOTS; ++s) c1.mid[s] = c0.mid[s];
+    }
     c1.valid = c0.valid;
     c1.acc = a.acc != 0;
     c1.data = c0.data;
@@ -631,7 +663,7 @@ __global__ __launch_bounds__((poisson_tile_B<T, L, TPL>() * TPL),
     c1.twd = twd;
     c1.t = t;
     c1.es = a.es;
-    LineFFT<T, L, TPL, decltype(c1), RLt>::run(c1);
+    LineFFT<T, L, TPL, decltype(c1), std::conditional_t<REG, RLi, RLt>>::run(c1);
 }
 
 // Lines are mapped as in ContigArgs; offsets count complex elements of the
