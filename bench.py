@@ -459,7 +459,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # Untimed warm-up: the MI355X reaches its steady memory throughput only after
+    # tens of milliseconds of sustained load (the 512^3 strided passes take
+    # 424 us in the first ~30 ms of a process, 400 us after 50 warm-up steps).
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--mode", choices=["fft", "copy", "batched", "poisson", "slab", "nd", "spectral", "serve", "oracle",
