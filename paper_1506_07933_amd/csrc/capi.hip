@@ -354,8 +354,41 @@ size_t mifft_poisson_ws_bytes(mifft_plan plan)
     return plan->poisson_ws_bytes;
 }
 
+// The side stream of caller stream s (created on first use, default
+// priority, non-blocking); nullptr where none can be used: s is being
+// captured into a graph and has no side stream yet (streams are not created
+// during a capture), or a creation failed.  Called with p.lane_mu held.
+static Plan::SideLane* side_lane(Plan& p, hipStream_t s)
+{
+    auto it = p.lanes.find(s);
+    if (it != p.lanes.end()) return &it->second;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    Plan::SideLane l;
+    if (hipStreamCreateWithFlags(&l.s, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (hipEventCreateWithFlags(&l.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&l.join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (l.fork) hipEventDestroy(l.fork);
+        hipStreamDestroy(l.s);
+        return nullptr;
+    }
+    return &(p.lanes[s] = l);
+}
+
+// Launches a pass list on stream s.  With lanes_ok, passes of lane 1 run on
+// a side stream of s: it starts after the lane 0 pass marked fork_after (or
+// at its first lane 1 pass), and the pass marked join_before -- or the end of
+// the call -- waits for it, so the call as a whole is still ordered on s.
+// Per-pass timing runs every pass on s.
 static int run_passes(const Plan& cp, const std::vector<Pass>& list, const void* in, void* out,
-                      void* ws, void* send, void* recv, hipStream_t s)
+                      void* ws, void* send, void* recv, hipStream_t s, bool lanes_ok = false)
 {
     Plan& p = const_cast<Plan&>(cp);
     hipEvent_t* ev = nullptr;
@@ -365,8 +398,36 @@ static int run_passes(const Plan& cp, const std::vector<Pass>& list, const void*
         ++p.prof_calls;
         hipEventRecord(ev[0], s);
     }
+    std::unique_lock<std::mutex> lane_lock;
+    Plan::SideLane* side = nullptr;
+    if (lanes_ok && !ev && std::any_of(list.begin(), list.end(), [](const Pass& q) { return q.lane == 1; })) {
+        lane_lock = std::unique_lock<std::mutex>(p.lane_mu);
+        side = side_lane(p, s);
+    }
+    bool fork_recorded = false, forked = false;
+    auto join = [&]() -> hipError_t {
+        forked = fork_recorded = false; // a later lane 1 pass forks anew
+        hipError_t e = hipEventRecord(side->join, side->s);
+        return e != hipSuccess ? e : hipStreamWaitEvent(s, side->join, 0);
+    };
     int qi = 0;
     for (const Pass& q : list) {
+        hipStream_t qs = s;
+        if (side) {
+            if (q.join_before && forked) {
+                hipError_t e = join();
+                if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "stream join: %s", hipGetErrorString(e));
+            }
+            if (q.lane == 1) {
+                if (!forked) {
+                    hipError_t e = fork_recorded ? hipSuccess : hipEventRecord(side->fork, s);
+                    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
+                    if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "stream fork: %s", hipGetErrorString(e));
+                    forked = true;
+                }
+                qs = side->s;
+            }
+        }
         auto res = [&](BufId b) -> void* {
             switch (b) {
             case B_IN: return const_cast<void*>(in);
@@ -385,9 +446,18 @@ static int run_passes(const Plan& cp, const std::vector<Pass>& list, const void*
         if (q.nyq_buf != B_NONE && !nyq)
             return set_error(MIFFT_ERR_INVALID, "internal: the Nyquist plane's buffer was not provided");
         if (nyq) nyq += q.nyq_off;
-        hipError_t e = launch_pass(q, p.prec, src, dst, s, nyq);
+        hipError_t e = launch_pass(q, p.prec, src, dst, qs, nyq);
         if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
         if (ev) hipEventRecord(ev[++qi], s);
+        if (side && q.fork_after && qs == s && !forked) {
+            if ((e = hipEventRecord(side->fork, s)) != hipSuccess)
+                return set_error(MIFFT_ERR_DEVICE, "stream fork: %s", hipGetErrorString(e));
+            fork_recorded = true;
+        }
+    }
+    if (side && forked) {
+        hipError_t e = join();
+        if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "stream join: %s", hipGetErrorString(e));
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
@@ -552,7 +622,10 @@ int mifft_spectral_apply(mifft_plan plan, int op, double alpha, const void* f, v
     }
     char* w = (char*)(ws ? ws : plan->ws);
     const size_t half = plan->poisson_ws_bytes / 2;
-    return run_passes(*plan, list, f, u, nullptr, w, w + half, (hipStream_t)stream);
+    // MIFFT_SIDE_STREAM=0 runs the Nyquist plane's passes in line (comparison)
+    const char* e = getenv("MIFFT_SIDE_STREAM");
+    const bool lanes = !(e && atoi(e) == 0);
+    return run_passes(*plan, list, f, u, nullptr, w, w + half, (hipStream_t)stream, lanes);
 }
 
 int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void* stream)
@@ -813,12 +886,13 @@ int mifft_plan_describe(mifft_plan plan, char* buf, size_t len)
         snprintf(line, sizeof(line),
                  "%s kind=%s axis=%c L=%d policy=%d tpl=%d sgn=%d lines=%lld lpw=%d B=%d cols=%d groups=%d "
                  "es=%lld/%lld gs=%lld/%lld off=%lld/%lld grid=%u block=%u lds=%zu pf=%d tpg=%d tiles=%d nt=%d "
-                 "nto=%d gdiv=%d/%d gs2=%lld/%lld pm=%u/%lld ni=%d is=%lld/%lld os=%lld/%lld\n",
+                 "nto=%d gdiv=%d/%d gs2=%lld/%lld pm=%u/%lld ni=%d is=%lld/%lld os=%lld/%lld lane=%d%s%s\n",
                  tag, kn[q.kind], "zyx-"[q.tag < 3 ? q.tag : 3], q.L, pol, tpl, q.sgn, q.nlines, q.lines_per_wg,
                  q.B, q.cols, q.groups, q.es_in, q.es_out, q.gs_in, q.gs_out, q.off_in, q.off_out, q.grid,
                  q.block, q.shmem, pf, q.tpg, q.ntiles, q.nt_in, q.nt_out, q.gdiv_in, q.gdiv_out, q.gs2_in,
                  q.gs2_out, q.kind == mifft::P_CONTIG_PACK ? q.fd.d : 0u, q.kind == mifft::P_CONTIG_PACK ? q.blk : 0,
-                 q.ni, q.is_o, q.is_i, q.os_o, q.os_i);
+                 q.ni, q.is_o, q.is_i, q.os_o, q.os_i, q.lane, q.fork_after ? " fork=1" : "",
+                 q.join_before ? " join=1" : "");
         s += line;
     };
     if (plan->pencil) {

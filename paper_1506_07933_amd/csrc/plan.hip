@@ -530,6 +530,11 @@ int get_twiddles(Plan& plan, int L, void** out)
 
 Plan::~Plan()
 {
+    for (auto& kv : lanes) {
+        hipStreamDestroy(kv.second.s);
+        hipEventDestroy(kv.second.fork);
+        hipEventDestroy(kv.second.join);
+    }
     for (hipEvent_t e : prof_events) hipEventDestroy(e);
     for (auto& kv : twiddles) hipFree(kv.second);
     if (ws) hipFree(ws);
@@ -1242,6 +1247,13 @@ void rebuild_poisson(Plan& plan)
             z.nyq_off = noff;
             z.nyq_o = 0;
             z.nyq_i = 1;
+            // the plane's passes touch only N: on large grids they run beside
+            // the main chain (lane 1) from the z-pass on, and the C2R waits
+            // for them.  Small solves keep them in line: there the fork and
+            // join cost more than the plane's launches (served mix of 64^3 -
+            // 512^3: median solve 0.164 -> 0.177 ms with them on a side stream;
+            // 512^3 FP32 1.046 -> 1.026 ms).
+            z.fork_after = (size_t)lines * M * plan.esz >= ((size_t)256 << 20);
         }
         plan.poisson.push_back(z);
         if (split) { // the Nyquist plane's y-lines: contiguous rows of N[x][k1]
@@ -1251,6 +1263,7 @@ void rebuild_poisson(Plan& plan)
             yn.tag = 1;
             yn.src = yn.dst = D;
             yn.off_in = yn.off_out = noff;
+            yn.lane = z.fork_after ? 1 : 0;
         }
         if (plan.n1 > 1) {
             Pass y;
@@ -1304,6 +1317,7 @@ void rebuild_poisson(Plan& plan)
                 xn.tag = 2;
                 xn.src = xn.dst = D;
                 xn.off_in = xn.off_out = noff;
+                xn.lane = yn.lane;
                 plan.poisson.push_back(xn);
                 plan.poisson_mul_n = 2;
             }
@@ -1339,6 +1353,7 @@ void rebuild_poisson(Plan& plan)
                 zi.nyq_off = noff;
                 zi.nyq_o = 1;
                 zi.nyq_i = plan.n1;
+                zi.join_before = yn.lane == 1;
             }
             plan.poisson.push_back(zi);
         }

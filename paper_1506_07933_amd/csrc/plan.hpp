@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -74,6 +75,11 @@ struct Pass {
     // byte offsets added to the resolved source / destination (chunked passes)
     long long off_in = 0, off_out = 0;
     int tag = 0; // 0 z, 1 y, 2 x, 3 other: for per-axis timing summaries
+    // Concurrency within a pass list (see run_passes): lane 1 passes may run on
+    // a side stream, after the lane 0 pass marked fork_after (or from the
+    // start of the call); a pass marked join_before waits for them.
+    int lane = 0;
+    bool fork_after = false, join_before = false;
     // launch geometry
     unsigned grid = 0, block = 0;
     size_t shmem = 0;
@@ -129,6 +135,14 @@ public:
     // opt-in per-pass event timing
     std::vector<hipEvent_t> prof_events; // max_calls * (max passes + 1)
     int prof_max_calls = 0, prof_calls = 0, prof_stride = 0, prof_npass = 0;
+    // side streams of the lane 1 passes, one per caller stream, with the
+    // fork and join events of that pair of streams
+    struct SideLane {
+        hipStream_t s = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+    };
+    std::map<hipStream_t, SideLane> lanes;
+    std::mutex lane_mu;
 
     ~Plan();
 };

@@ -283,6 +283,22 @@ def test_poisson_chain_with_the_nyquist_plane_apart():
     assert pws == 2 * (noff + 512 * 512 * 8)
 
 
+def test_poisson_plane_passes_run_beside_the_main_chain_on_large_grids():
+    """The Nyquist plane's three passes (lane 1) run on a side stream after the
+    z-pass (fork) and before the C2R (join) where the half spectrum is at
+    least 256 MiB; smaller solves run every pass in line."""
+    passes, _, _ = plan_only(512, 512, 512, kind=1, prec=0)
+    po = [p for p in passes if p["dir"] == "poisson"]
+    assert [p["lane"] for p in po] == ["0", "0", "1", "0", "1", "1", "0", "0"]
+    assert [p.get("fork") for p in po] == ["1"] + [None] * 7
+    assert [p.get("join") for p in po] == [None] * 7 + ["1"]
+    for shape in ((64, 64, 64), (256, 256, 256)):
+        passes, _, _ = plan_only(*shape, kind=1, prec=0)
+        po = [p for p in passes if p["dir"] == "poisson"]
+        assert all(p["lane"] == "0" and "fork" not in p and "join" not in p for p in po)
+    assert len(po) == 8  # 256^3 keeps the plane apart, in line
+
+
 def test_plan_only_cannot_execute():
     h = ctypes.c_void_p()
     assert lib.mifft_plan_create(ctypes.byref(h), 8, 8, 8, 0, 0, MIFFT_PLAN_ONLY) == 0
