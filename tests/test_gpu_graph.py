@@ -81,6 +81,45 @@ def test_poisson_graph_transposed(prec):
     p.close()
 
 
+def test_poisson_graph_with_the_side_stream(monkeypatch):
+    """A 512^3 FP32 solve runs the Nyquist plane's passes on a side stream
+    (fork after the z-pass, join before the C2R).  Captured on a stream that
+    already has its side stream (an eager call on it first), the graph holds
+    both branches: every replay equals the eager result bit for bit, and so
+    does the solve with every pass in line (same kernels on the same data)."""
+    from paper_1506_07933_amd import Plan
+    shape = (512, 512, 512)
+    f64 = synth.normal_real(shape, np.float64, seed=9)
+    f = torch.from_numpy((f64 - f64.mean()).astype(np.float32)).cuda()
+    del f64
+    u = torch.empty_like(f)
+    p = Plan(shape, "r2c", "fp32")
+    assert "fork=1" in p.describe() and "join=1" in p.describe()
+    ws = torch.empty(p.poisson_ws_bytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        p.poisson(f, out=u, ws=ws)  # creates the side stream of s
+    s.synchronize()
+    ref = u.clone()
+    monkeypatch.setenv("MIFFT_SIDE_STREAM", "0")
+    u.fill_(3.0)
+    p.poisson(f, out=u, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(u, ref), "in-line solve differs"
+    monkeypatch.delenv("MIFFT_SIDE_STREAM")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        p.poisson(f, out=u, ws=ws)
+    for r in range(3):
+        u.fill_(float(r + 7))  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref), "replay %d differs" % r
+    del g
+    p.close()
+
+
 def test_spectral_gradient_divergence_graph():
     """Gradient and divergence (several launches over a caller workspace)
     captured together and replayed."""
