@@ -745,25 +745,23 @@ __global__ __launch_bounds__(1024) void k_c2r_z(RealArgs<T> a)
     c.out = reinterpret_cast<V*>(a.out) + lo * a.os_o + li * a.os_i;
     if (c.valid) {
         const V* in = reinterpret_cast<const V*>(a.in) + lo * a.is_o + li * a.is_i;
-        if constexpr (sizeof(T) == 4) {
-            // FP32: all loads of the line in flight before the first LDS store
-            // (512^3 Poisson solve 1.25 -> 1.20 ms; in FP64 this order made
-            // the 256^3 C2R slower, 0.18 -> 0.22 ms)
-            constexpr int NK = (L + 1 + TPL - 1) / TPL;
-            V v[NK];
+        // all loads of the line in flight before the first LDS store (512^3
+        // Poisson solve FP32 1.25 -> 1.20 ms), held as native two-element
+        // vectors: an array of cx<double> here was kept in scratch memory
+        typedef typename nt2_of<T>::type N2;
+        constexpr int NK = (L + 1 + TPL - 1) / TPL;
+        N2 v[NK];
 #pragma unroll
-            for (int i = 0; i < NK; ++i) {
-                const int k = c.t + i * TPL;
-                if (k <= L) v[i] = (k == L && a.nyq) ? a.nyq[lo * a.nyq_o + li * a.nyq_i] : in[k];
-            }
+        for (int i = 0; i < NK; ++i) {
+            const int k = c.t + i * TPL;
+            if (k <= L)
+                v[i] = *reinterpret_cast<const N2*>((k == L && a.nyq) ? a.nyq + (lo * a.nyq_o + li * a.nyq_i)
+                                                                      : in + k);
+        }
 #pragma unroll
-            for (int i = 0; i < NK; ++i) {
-                const int k = c.t + i * TPL;
-                if (k <= L) c.lds[lds_pad(k)] = v[i];
-            }
-        } else {
-            for (int k = c.t; k <= L; k += TPL)
-                c.lds[lds_pad(k)] = (k == L && a.nyq) ? a.nyq[lo * a.nyq_o + li * a.nyq_i] : in[k];
+        for (int i = 0; i < NK; ++i) {
+            const int k = c.t + i * TPL;
+            if (k <= L) c.lds[lds_pad(k)] = V{v[i].x, v[i].y};
         }
     }
     c.sync();
