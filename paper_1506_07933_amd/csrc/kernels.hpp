@@ -746,9 +746,11 @@ __global__ __launch_bounds__(1024) void k_c2r_z(RealArgs<T> a)
     if (c.valid) {
         const V* in = reinterpret_cast<const V*>(a.in) + lo * a.is_o + li * a.is_i;
         // all loads of the line in flight before the first LDS store (512^3
-        // Poisson solve FP32 1.25 -> 1.20 ms), held as native two-element
-        // vectors: an array of cx<double> here was kept in scratch memory
-        typedef typename nt2_of<T>::type N2;
+        // Poisson solve FP32 1.25 -> 1.20 ms).  FP64 holds them as native
+        // two-element vectors (an array of cx<double> here was kept in scratch
+        // memory), FP32 as cx<float> (native float vectors were, for the
+        // lengths with many elements per thread).
+        typedef std::conditional_t<sizeof(T) == 8, typename nt2_of<T>::type, V> N2;
         constexpr int NK = (L + 1 + TPL - 1) / TPL;
         N2 v[NK];
 #pragma unroll
