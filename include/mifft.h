@@ -302,6 +302,13 @@ int mifft_poisson_solve(mifft_plan plan, const void* f, void* u, void* ws, void*
  * of mifft_poisson_ws_bytes (apply) or mifft_spectral_ws_bytes (gradient,
  * divergence) bytes.  Errors: BADPLAN for a plan that is not a 3-D R2C
  * plan, INVALID for NULL / unaligned / aliased fields or an unknown op.
+ * On plans whose half spectrum is 256 MiB or more, mifft_spectral_apply and
+ * mifft_poisson_solve run the k2 = n2/2 plane's passes on a side stream that
+ * the plan created with itself (one of four, taken by a caller stream at its
+ * first such call and kept): it waits for `stream`, and `stream` waits for
+ * it before the last pass, so the call is still ordered on `stream` and may
+ * be captured.  Calls on a fifth distinct stream run those passes on
+ * `stream` itself.
  */
 #define MIFFT_OP_POISSON 0
 #define MIFFT_OP_LAPLACIAN 1

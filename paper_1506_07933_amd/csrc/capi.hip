@@ -104,6 +104,8 @@ static int finish_plan(Plan* p, mifft_plan* out)
 
 extern "C" {
 
+static int create_lanes(Plan& p);
+
 int mifft_plan_create(mifft_plan* out, int n0, int n1, int n2, int kind, int prec, unsigned flags)
 {
     clear_error();
@@ -150,6 +152,10 @@ int mifft_plan_create(mifft_plan* out, int n0, int n1, int n2, int kind, int pre
             return set_error(MIFFT_ERR_NOMEM, "workspace of %zu bytes: %s", p->default_ws_bytes,
                              hipGetErrorString(e));
         }
+    }
+    if ((rc = create_lanes(*p))) {
+        delete p;
+        return rc;
     }
     return finish_plan(p, out);
 }
@@ -354,32 +360,34 @@ size_t mifft_poisson_ws_bytes(mifft_plan plan)
     return plan->poisson_ws_bytes;
 }
 
-// The side stream of caller stream s (created on first use, default
-// priority, non-blocking); nullptr where none can be used: s is being
-// captured into a graph and has no side stream yet (streams are not created
-// during a capture), or a creation failed.  Called with p.lane_mu held.
+// The side lane of caller stream s: the one it took before, else the next
+// free one of the plan's pool; nullptr when the pool is used up (the call
+// then runs its list in line).  Creates nothing.  Called with p.lane_mu held.
 static Plan::SideLane* side_lane(Plan& p, hipStream_t s)
 {
     auto it = p.lanes.find(s);
-    if (it != p.lanes.end()) return &it->second;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
-        (void)hipGetLastError();
-        return nullptr;
+    if (it != p.lanes.end()) return &p.lane_pool[it->second];
+    if (p.lanes.size() >= p.lane_pool.size()) return nullptr;
+    const int i = (int)p.lanes.size();
+    p.lanes[s] = i;
+    return &p.lane_pool[i];
+}
+
+// The side lanes of a plan whose pass lists have lane 1 passes (default
+// priority, non-blocking streams; events without timing).
+static int create_lanes(Plan& p)
+{
+    bool any = false;
+    for (const Pass& q : p.poisson) any = any || q.lane == 1;
+    if (!any) return MIFFT_OK;
+    p.lane_pool.resize(Plan::kLanePool);
+    for (Plan::SideLane& l : p.lane_pool) {
+        hipError_t e = hipStreamCreateWithFlags(&l.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&l.fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&l.join, hipEventDisableTiming);
+        if (e != hipSuccess) return set_error(MIFFT_ERR_DEVICE, "side stream: %s", hipGetErrorString(e));
     }
-    Plan::SideLane l;
-    if (hipStreamCreateWithFlags(&l.s, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    if (hipEventCreateWithFlags(&l.fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&l.join, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGetLastError();
-        if (l.fork) hipEventDestroy(l.fork);
-        hipStreamDestroy(l.s);
-        return nullptr;
-    }
-    return &(p.lanes[s] = l);
+    return MIFFT_OK;
 }
 
 // Launches a pass list on stream s.  With lanes_ok, passes of lane 1 run on

@@ -530,10 +530,10 @@ int get_twiddles(Plan& plan, int L, void** out)
 
 Plan::~Plan()
 {
-    for (auto& kv : lanes) {
-        hipStreamDestroy(kv.second.s);
-        hipEventDestroy(kv.second.fork);
-        hipEventDestroy(kv.second.join);
+    for (SideLane& l : lane_pool) {
+        if (l.s) hipStreamDestroy(l.s);
+        if (l.fork) hipEventDestroy(l.fork);
+        if (l.join) hipEventDestroy(l.join);
     }
     for (hipEvent_t e : prof_events) hipEventDestroy(e);
     for (auto& kv : twiddles) hipFree(kv.second);

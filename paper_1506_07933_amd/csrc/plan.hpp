@@ -135,13 +135,16 @@ public:
     // opt-in per-pass event timing
     std::vector<hipEvent_t> prof_events; // max_calls * (max passes + 1)
     int prof_max_calls = 0, prof_calls = 0, prof_stride = 0, prof_npass = 0;
-    // side streams of the lane 1 passes, one per caller stream, with the
-    // fork and join events of that pair of streams
+    // side streams of the lane 1 passes with the fork and join events of each,
+    // created with the plan (kLanePool of them where a pass list has lane 1
+    // passes); a caller stream takes one at its first such call and keeps it
     struct SideLane {
         hipStream_t s = nullptr;
         hipEvent_t fork = nullptr, join = nullptr;
     };
-    std::map<hipStream_t, SideLane> lanes;
+    static constexpr int kLanePool = 4;
+    std::vector<SideLane> lane_pool;
+    std::map<hipStream_t, int> lanes; // caller stream -> index into lane_pool
     std::mutex lane_mu;
 
     ~Plan();

@@ -116,7 +116,17 @@ def test_poisson_graph_with_the_side_stream(monkeypatch):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(u, ref), "replay %d differs" % r
-    del g
+    # captured on a stream that has made no call before (it takes its side
+    # stream from the plan's pool inside the capture)
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        p.poisson(f, out=u, ws=ws)
+    for r in range(2):
+        u.fill_(float(r + 11))
+        g2.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref), "replay %d of the second graph differs" % r
+    del g, g2
     p.close()
 
 
