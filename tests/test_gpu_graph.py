@@ -130,6 +130,31 @@ def test_poisson_graph_with_the_side_stream(monkeypatch):
     p.close()
 
 
+def test_poisson_side_streams_per_caller_stream():
+    """A 512^3 FP32 plan holds four side streams; calls on five distinct
+    caller streams (the fifth runs the plane's passes in line) and on the
+    default stream all give the same result bit for bit."""
+    from paper_1506_07933_amd import Plan
+    shape = (512, 512, 512)
+    f = torch.empty(shape, dtype=torch.float32, device="cuda")
+    synth.poisson_rhs_device(f, seed=3)
+    u = torch.empty_like(f)
+    p = Plan(shape, "r2c", "fp32")
+    ws = torch.empty(p.poisson_ws_bytes, dtype=torch.uint8, device="cuda")
+    p.poisson(f, out=u, ws=ws)
+    torch.cuda.synchronize()
+    ref = u.clone()
+    streams = [torch.cuda.Stream() for _ in range(5)]
+    for i, st in enumerate(streams):
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            u.fill_(float(i + 1))
+            p.poisson(f, out=u, ws=ws)
+        st.synchronize()
+        assert torch.equal(u, ref), "stream %d differs" % i
+    p.close()
+
+
 def test_spectral_gradient_divergence_graph():
     """Gradient and divergence (several launches over a caller workspace)
     captured together and replayed."""
