@@ -486,8 +486,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the local FFT phases run on a single MI355X and this "
-              "build has no multi-GPU exchange; run it with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the local FFT phases run on a single MI355X and the "
+              "library has no multi-GPU exchange; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.mode == "copy":
         return copy_mode(args)
